@@ -1,0 +1,488 @@
+/*
+ * Plain FP64 CPU oracle of the advection-diffusion lattice Boltzmann model coupled to the
+ * Maxwell-Stefan equations through a per-node relaxation time (Huang, Bao, Jiang, Zhang,
+ * "A combined approach of LBM and Maxwell-Stefan equation for modeling multi-component
+ * diffusion in SOFC", arXiv 1809.01600).
+ *
+ * TEST INFRASTRUCTURE.  This file exists only to check the HIP library; it is slow on purpose
+ * and shares no code, header, table or helper with it.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.
+ *
+ * State: the pre-collision populations f[s][a][node] of the two evolved species s = 0 (H2) and
+ * s = 1 (H2O); the inert third species (Ar) is the balance X_3 = 1 - X_1 - X_2.  node index =
+ * (z * ny + y) * nx + x, x = diffusion direction (Dirichlet inlet at x = 0, reactive-flux outlet
+ * at x = nx - 1), periodic in y and z.  Entries of solid nodes are ignored and written as 0.
+ *
+ * One step, in the paper's order (Eq. 28: collide, then stream):
+ *   1. moments X_s = sum_a f_a (Eq. 29 makes f a mole-fraction distribution); X_3 by closure
+ *      (Sec. 3.2, last paragraph).
+ *   2. mole-fraction gradients in lattice units (Eq. 35 in x at the inlet column, Eq. 37 at the
+ *      outlet column, central differences elsewhere, one-sided next to solid).
+ *   3. Maxwell-Stefan matrix [B] (Eq. 32), generalized Fick fluxes J = -[B]^-1 grad X with
+ *      Gamma = I (Eq. 30, 33, 34); N = J since the total molar flux is zero (Eq. 21 with u_M = 0).
+ *   4. effective diffusivity of each evolved species from Eq. 24 with the flux vectors replaced
+ *      by signed norms N_i -> -sgn(nu_i) |N_i|.
+ *   5. relaxation time tau_i = D_i / c_s^2 + 1/2 with c_s^2 = 1/3 (Eq. 25).
+ *   6. BGK collision toward f_eq = w_a X_s (Eq. 28 with Eq. 29).
+ *   7. streaming; half-way bounce-back on solid links (Sec. 3.3, last paragraph).
+ *   8. inlet: anti-bounce-back f_a = (w_a + w_abar) X_in - f_abar (Eq. 36);
+ *      outlet: exact-flux rule f_a = f*_abar - (w_abar / W_n) Q_s imposing the electrode flux
+ *      N_s = -nu_s I / (n F) (Eq. 39) as the net lattice outflow Q_s per open outlet node.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int lattice;          /* 0: D2Q9, 1: D3Q19 */
+    int nx, ny, nz;       /* nz = 1 for D2Q9 */
+    double Dl[3][3];      /* lattice binary diffusivities D*_ij = D_ij dt / dx^2 (symmetric) */
+    double X_in[2];       /* inlet mole fractions of the evolved species */
+    double Q[2];          /* lattice outflow per open outlet node per step, evolved species */
+    double nu[3];         /* stoichiometric coefficients (Eq. 39) */
+    int inlet_wall;       /* 1: the inlet face is a bounce-back wall (closed-box tests) */
+    int ms_mode;          /* 0: flux-norm ratio from the local fluxes, 1: stoichiometric ratio */
+    double eps;           /* regularizer of the flux-norm ratio (lattice units) */
+    double tau_min, tau_max;
+} orc_params;
+
+typedef struct {
+    double inflow[2];     /* amount entering through the inlet face during the step */
+    double outflow[2];    /* amount leaving through the outlet face during the step */
+    long clamp_hits;      /* relaxation times that hit tau_min or tau_max */
+} orc_stats;
+
+#define ORC_QMAX 19
+
+typedef struct {
+    int q;
+    int e[ORC_QMAX][3];
+    double w[ORC_QMAX];
+    int opp[ORC_QMAX];
+    double Wn;            /* sum of the weights of the velocities with e_x = +1 */
+} orc_lattice;
+
+/* D2Q9 from Eq. 2 and Eq. 9; D3Q19 by enumerating the vectors of {-1,0,1}^3 with |e|^2 <= 2
+ * (rest, then the six axis vectors, then the twelve edge vectors) with weights 1/3, 1/18, 1/36. */
+static void build_lattice(int lattice, orc_lattice* L)
+{
+    memset(L, 0, sizeof(*L));
+    if (lattice == 0) {
+        L->q = 9;
+        for (int a = 0; a < 9; ++a) {
+            double ex = 0.0, ey = 0.0;
+            if (a >= 1 && a <= 4) {
+                ex = cos((a - 1) * M_PI / 2.0);
+                ey = sin((a - 1) * M_PI / 2.0);
+            } else if (a >= 5) {
+                ex = sqrt(2.0) * cos((a - 5) * M_PI / 2.0 + M_PI / 4.0);
+                ey = sqrt(2.0) * sin((a - 5) * M_PI / 2.0 + M_PI / 4.0);
+            }
+            L->e[a][0] = (int)lround(ex);
+            L->e[a][1] = (int)lround(ey);
+            L->e[a][2] = 0;
+            L->w[a] = (a == 0) ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+        }
+    } else {
+        int n = 0;
+        for (int len2 = 0; len2 <= 2; ++len2)
+            for (int ez = -1; ez <= 1; ++ez)
+                for (int ey = -1; ey <= 1; ++ey)
+                    for (int ex = -1; ex <= 1; ++ex) {
+                        if (ex * ex + ey * ey + ez * ez != len2) continue;
+                        L->e[n][0] = ex;
+                        L->e[n][1] = ey;
+                        L->e[n][2] = ez;
+                        L->w[n] = (len2 == 0) ? 1.0 / 3.0 : (len2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                        ++n;
+                    }
+        L->q = n; /* 19 */
+    }
+    for (int a = 0; a < L->q; ++a) {
+        for (int b = 0; b < L->q; ++b)
+            if (L->e[b][0] == -L->e[a][0] && L->e[b][1] == -L->e[a][1] && L->e[b][2] == -L->e[a][2])
+                L->opp[a] = b;
+        if (L->e[a][0] == 1) L->Wn += L->w[a];
+    }
+}
+
+int orc_num_velocities(int lattice)
+{
+    orc_lattice L;
+    build_lattice(lattice, &L);
+    return L.q;
+}
+
+void orc_velocities(int lattice, int* e, double* w)
+{
+    orc_lattice L;
+    build_lattice(lattice, &L);
+    for (int a = 0; a < L.q; ++a) {
+        e[3 * a + 0] = L.e[a][0];
+        e[3 * a + 1] = L.e[a][1];
+        e[3 * a + 2] = L.e[a][2];
+        w[a] = L.w[a];
+    }
+}
+
+static int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+static long node_index(const orc_params* p, int x, int y, int z)
+{
+    return ((long)z * p->ny + y) * p->nx + x;
+}
+
+/* sign convention of Eq. 24: N_i = -(nu_i / |nu_i|) |N_i|; zero for an inert species */
+static double flux_sign(double nu)
+{
+    if (nu > 0.0) return -1.0;
+    if (nu < 0.0) return 1.0;
+    return 0.0;
+}
+
+/* Moments of all nodes: X[k][node], k = 0, 1 evolved species, k = 2 the balance species. */
+void orc_moments(const orc_params* p, const uint8_t* solid, const double* f, double* X)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    long N = (long)p->nx * p->ny * p->nz;
+    for (long n = 0; n < N; ++n) {
+        if (solid[n]) {
+            X[n] = X[N + n] = X[2 * N + n] = 0.0;
+            continue;
+        }
+        double xs[2];
+        for (int s = 0; s < 2; ++s) {
+            double sum = 0.0;
+            for (int a = 0; a < L.q; ++a) sum += f[((long)s * L.q + a) * N + n];
+            xs[s] = sum;
+        }
+        X[n] = xs[0];
+        X[N + n] = xs[1];
+        X[2 * N + n] = 1.0 - xs[0] - xs[1];
+    }
+}
+
+/* Is (x, y, z) an existing fluid node?  y and z wrap; x does not. */
+static int is_fluid(const orc_params* p, const uint8_t* solid, int x, int y, int z)
+{
+    if (x < 0 || x >= p->nx) return 0;
+    return !solid[node_index(p, x, wrap(y, p->ny), wrap(z, p->nz))];
+}
+
+/* Eq. 32: the (n-1)x(n-1) matrix [B] for n = 3 species, from the full composition X[0..2]. */
+static void ms_matrix(const orc_params* p, const double X[3], double B[2][2])
+{
+    const int n = 2; /* index of the last (balance) species */
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            if (i == j) {
+                double b = X[i] / p->Dl[i][n];
+                for (int k = 0; k < 3; ++k)
+                    if (k != i) b += X[k] / p->Dl[i][k];
+                B[i][i] = b;
+            } else {
+                B[i][j] = -X[i] * (1.0 / p->Dl[i][j] - 1.0 / p->Dl[i][n]);
+            }
+        }
+}
+
+/*
+ * Steps 1-6 for every fluid node: f (pre-collision) -> fstar (post-collision).
+ * Optionally returns the relaxation times tau[s][node] and the fluxes J[s][d][node].
+ */
+static int collide_all(const orc_params* p, const orc_lattice* L, const uint8_t* solid,
+                       const double* f, double* fstar, double* tau_out, double* J_out,
+                       long* clamp_hits)
+{
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int q = L->q;
+    const int dims = (p->lattice == 0) ? 2 : 3;
+    double* X = (double*)malloc(sizeof(double) * 3 * N);
+    if (!X) return -8;
+    orc_moments(p, solid, f, X);
+    long hits = 0;
+
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const long n = node_index(p, x, y, z);
+                if (solid[n]) {
+                    for (int s = 0; s < 2; ++s)
+                        for (int a = 0; a < q; ++a) fstar[((long)s * q + a) * N + n] = 0.0;
+                    continue;
+                }
+                double Xn[3] = {X[n], X[N + n], X[2 * N + n]};
+                double B[2][2];
+                ms_matrix(p, Xn, B);
+
+                /* step 2: gradients g[s][d] in lattice units */
+                double g[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                for (int d = 0; d < dims; ++d) {
+                    if (d == 0 && x == p->nx - 1) {
+                        /* Eq. 37: grad X = -C_t^-1 [D]^-1 J = -[B] J with the imposed flux */
+                        for (int s = 0; s < 2; ++s)
+                            g[s][0] = -(B[s][0] * p->Q[0] + B[s][1] * p->Q[1]);
+                        continue;
+                    }
+                    int up[3] = {x, y, z}, dn[3] = {x, y, z};
+                    up[d] += 1;
+                    dn[d] -= 1;
+                    int fu = is_fluid(p, solid, up[0], up[1], up[2]);
+                    int fd = is_fluid(p, solid, dn[0], dn[1], dn[2]);
+                    for (int s = 0; s < 2; ++s) {
+                        double xc = X[(long)s * N + n];
+                        double xu = fu ? X[(long)s * N + node_index(p, up[0], wrap(up[1], p->ny), wrap(up[2], p->nz))] : 0.0;
+                        double xd = fd ? X[(long)s * N + node_index(p, dn[0], wrap(dn[1], p->ny), wrap(dn[2], p->nz))] : 0.0;
+                        if (fu && fd)
+                            g[s][d] = 0.5 * (xu - xd);
+                        else if (fu)
+                            g[s][d] = xu - xc;   /* forward (Eq. 35 at the inlet column) */
+                        else if (fd)
+                            g[s][d] = xc - xd;
+                        else
+                            g[s][d] = 0.0;
+                    }
+                }
+
+                /* step 3: J = -[B]^-1 g per axis (Cramer's rule) */
+                double det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+                double J[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                for (int d = 0; d < dims; ++d) {
+                    J[0][d] = -(B[1][1] * g[0][d] - B[0][1] * g[1][d]) / det;
+                    J[1][d] = -(B[0][0] * g[1][d] - B[1][0] * g[0][d]) / det;
+                }
+                double norm[2];
+                for (int s = 0; s < 2; ++s) {
+                    double ss = 0.0;
+                    for (int d = 0; d < dims; ++d) ss += J[s][d] * J[s][d];
+                    norm[s] = sqrt(ss);
+                }
+
+                /* steps 4-5: Eq. 24 with signed flux norms, Eq. 25 */
+                double tau[2];
+                for (int i = 0; i < 2; ++i) {
+                    double inv_D = 0.0;
+                    double si = flux_sign(p->nu[i]);
+                    for (int j = 0; j < 3; ++j) {
+                        if (j == i) continue;
+                        double sj = flux_sign(p->nu[j]);
+                        double ratio = 0.0; /* N_j / N_i */
+                        if (sj != 0.0) {
+                            double rho;
+                            if (p->ms_mode == 1)
+                                rho = fabs(p->nu[j]) / fabs(p->nu[i]);
+                            else
+                                rho = (norm[j] + p->eps * fabs(p->nu[j])) /
+                                      (norm[i] + p->eps * fabs(p->nu[i]));
+                            ratio = (sj / si) * rho;
+                        }
+                        inv_D += (Xn[j] - Xn[i] * ratio) / p->Dl[i][j];
+                    }
+                    double D = 1.0 / inv_D;
+                    double t = 3.0 * D + 0.5;
+                    if (!(t >= p->tau_min)) { t = p->tau_min; ++hits; }
+                    else if (t > p->tau_max) { t = p->tau_max; ++hits; }
+                    tau[i] = t;
+                }
+                if (tau_out) {
+                    tau_out[n] = tau[0];
+                    tau_out[N + n] = tau[1];
+                }
+                if (J_out)
+                    for (int s = 0; s < 2; ++s)
+                        for (int d = 0; d < 3; ++d) J_out[((long)s * 3 + d) * N + n] = J[s][d];
+
+                /* step 6: BGK collision toward w_a X_s */
+                for (int s = 0; s < 2; ++s)
+                    for (int a = 0; a < q; ++a) {
+                        long k = ((long)s * q + a) * N + n;
+                        fstar[k] = f[k] - (f[k] - L->w[a] * Xn[s]) / tau[s];
+                    }
+            }
+    free(X);
+    if (clamp_hits) *clamp_hits = hits;
+    return 0;
+}
+
+/* Steps 1-6 only (post-collision populations of the current state). */
+int orc_collide(const orc_params* p, const uint8_t* solid, const double* f, double* fstar,
+                double* tau_out, double* J_out, orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    long hits = 0;
+    int rc = collide_all(p, &L, solid, f, fstar, tau_out, J_out, &hits);
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->clamp_hits = hits;
+    }
+    return rc;
+}
+
+/* Steps 7-8: stream fstar into fnext with bounce-back and the two x boundaries. */
+static void stream_all(const orc_params* p, const orc_lattice* L, const uint8_t* solid,
+                       const double* fstar, double* fnext, orc_stats* st)
+{
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int q = L->q;
+    double inflow[2] = {0, 0}, outflow[2] = {0, 0};
+
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const long n = node_index(p, x, y, z);
+                if (solid[n]) {
+                    for (int s = 0; s < 2; ++s)
+                        for (int a = 0; a < q; ++a) fnext[((long)s * q + a) * N + n] = 0.0;
+                    continue;
+                }
+                int kind[ORC_QMAX]; /* 0 streamed or bounced, 1 inlet link, 2 outlet link */
+                for (int a = 0; a < q; ++a) {
+                    int sx = x - L->e[a][0];
+                    int sy = wrap(y - L->e[a][1], p->ny);
+                    int sz = wrap(z - L->e[a][2], p->nz);
+                    kind[a] = 0;
+                    if (sx < 0) { kind[a] = 1; continue; }
+                    if (sx >= p->nx) { kind[a] = 2; continue; }
+                    long src = node_index(p, sx, sy, sz);
+                    for (int s = 0; s < 2; ++s) {
+                        if (solid[src])
+                            fnext[((long)s * q + a) * N + n] = fstar[((long)s * q + L->opp[a]) * N + n];
+                        else
+                            fnext[((long)s * q + a) * N + n] = fstar[((long)s * q + a) * N + src];
+                    }
+                }
+                for (int a = 0; a < q; ++a) {
+                    int b = L->opp[a];
+                    for (int s = 0; s < 2; ++s) {
+                        double* dst = &fnext[((long)s * q + a) * N + n];
+                        double out_pop = fstar[((long)s * q + b) * N + n]; /* leaves through the face */
+                        if (kind[a] == 1) {
+                            if (p->inlet_wall)
+                                *dst = out_pop;
+                            else
+                                *dst = (L->w[a] + L->w[b]) * p->X_in[s] - fnext[((long)s * q + b) * N + n];
+                            inflow[s] += *dst - out_pop;
+                        } else if (kind[a] == 2) {
+                            *dst = out_pop - (L->w[b] / L->Wn) * p->Q[s];
+                            outflow[s] += out_pop - *dst;
+                        }
+                    }
+                }
+            }
+    if (st) {
+        for (int s = 0; s < 2; ++s) {
+            st->inflow[s] = inflow[s];
+            st->outflow[s] = outflow[s];
+        }
+    }
+}
+
+/* One full step f -> fnext.  Returns 0, or -8 when memory runs out. */
+int orc_step(const orc_params* p, const uint8_t* solid, const double* f, double* fnext,
+             orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long N = (long)p->nx * p->ny * p->nz;
+    double* fstar = (double*)malloc(sizeof(double) * 2 * L.q * N);
+    if (!fstar) return -8;
+    long hits = 0;
+    int rc = collide_all(p, &L, solid, f, fstar, NULL, NULL, &hits);
+    if (rc == 0) {
+        orc_stats tmp;
+        memset(&tmp, 0, sizeof(tmp));
+        stream_all(p, &L, solid, fstar, fnext, &tmp);
+        tmp.clamp_hits = hits;
+        if (st) *st = tmp;
+    }
+    free(fstar);
+    return rc;
+}
+
+/* nsteps steps in place on f (work must hold as many doubles as f).  Stats of the last step. */
+int orc_run(const orc_params* p, const uint8_t* solid, double* f, double* work, long nsteps,
+            orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long total = 2L * L.q * p->nx * p->ny * p->nz;
+    long hits = 0;
+    for (long t = 0; t < nsteps; ++t) {
+        orc_stats s1;
+        int rc = orc_step(p, solid, f, work, &s1);
+        if (rc) return rc;
+        memcpy(f, work, sizeof(double) * total);
+        hits += s1.clamp_hits;
+        if (st) *st = s1;
+    }
+    if (st) st->clamp_hits = hits;
+    return 0;
+}
+
+/* Equilibrium initial state f_a = w_a X0_s for fluid nodes (X0 holds [3][N] or [2][N]). */
+void orc_equilibrium(const orc_params* p, const uint8_t* solid, const double* X0, double* f)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long N = (long)p->nx * p->ny * p->nz;
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < L.q; ++a)
+            for (long n = 0; n < N; ++n)
+                f[((long)s * L.q + a) * N + n] = solid[n] ? 0.0 : L.w[a] * X0[(long)s * N + n];
+}
+
+/*
+ * Pore-space clean-up: fluid nodes that no chain of lattice links (periodic in y and z, not in
+ * x) connects to a fluid node of the inlet column become solid.  Returns the number of fluid
+ * nodes left in the outlet column (0 means the outlet cannot be reached).
+ */
+long orc_label(int lattice, int nx, int ny, int nz, const uint8_t* solid_in, uint8_t* solid_out)
+{
+    orc_lattice L;
+    build_lattice(lattice, &L);
+    const long N = (long)nx * ny * nz;
+    uint8_t* seen = (uint8_t*)calloc(N, 1);
+    long* queue = (long*)malloc(sizeof(long) * N);
+    if (!seen || !queue) {
+        free(seen);
+        free(queue);
+        return -8;
+    }
+    long head = 0, tail = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            long n = ((long)z * ny + y) * nx;
+            if (!solid_in[n]) {
+                seen[n] = 1;
+                queue[tail++] = n;
+            }
+        }
+    while (head < tail) {
+        long n = queue[head++];
+        int x = (int)(n % nx);
+        int y = (int)((n / nx) % ny);
+        int z = (int)(n / ((long)nx * ny));
+        for (int a = 1; a < L.q; ++a) {
+            int xx = x + L.e[a][0];
+            if (xx < 0 || xx >= nx) continue;
+            int yy = wrap(y + L.e[a][1], ny);
+            int zz = wrap(z + L.e[a][2], nz);
+            long m = ((long)zz * ny + yy) * nx + xx;
+            if (!solid_in[m] && !seen[m]) {
+                seen[m] = 1;
+                queue[tail++] = m;
+            }
+        }
+    }
+    long outlet = 0;
+    for (long n = 0; n < N; ++n) {
+        solid_out[n] = seen[n] ? 0 : 1;
+        if (seen[n] && (n % nx) == nx - 1) ++outlet;
+    }
+    free(seen);
+    free(queue);
+    return outlet;
+}

@@ -1,0 +1,395 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU needed).
+
+Every test here checks the oracle against something other than itself: closed forms, exact
+discrete identities, conservation, symmetry, or a library routine.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import closed_forms as cf
+from paper_1809_01600_amd import inputs
+
+
+def _uniform(o, X):
+    X0 = np.zeros((3,) + o.case.shape)
+    for s in range(3):
+        X0[s] = X[s]
+    return X0
+
+
+def run_to_steady(o, window=2000, tol=1e-15, max_steps=2_000_000):
+    Xp = o.moments()
+    steps = 0
+    while steps < max_steps:
+        o.step(window)
+        steps += window
+        X = o.moments()
+        r = oracle.residual(X, Xp, o.fluid(), window)
+        Xp = X
+        if r < tol:
+            return X, r
+    raise AssertionError("no steady state within %d steps (r=%g)" % (max_steps, r))
+
+
+# ----------------------------------------------------------------------------------------------
+# velocity sets (Eq. 2, Eq. 9; D3Q19 moments)
+# ----------------------------------------------------------------------------------------------
+
+def test_d2q9_matches_eq2_eq9():
+    e, w = oracle.velocities("D2Q9")
+    assert e[:, :2].tolist() == [[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1],
+                                 [1, 1], [-1, 1], [-1, -1], [1, -1]]
+    assert np.allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19)])
+def test_velocity_set_isotropy(lat, q):
+    e, w = oracle.velocities(lat)
+    d = 2 if lat == "D2Q9" else 3
+    assert len(w) == q
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose((w[:, None] * e).sum(0), 0.0, atol=1e-16)
+    M2 = (w[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0)[:d, :d]
+    assert np.allclose(M2, np.eye(d) / 3.0, atol=1e-15)
+    # D1Q3 marginal along x: weights 1/6, 2/3, 1/6 (used by the exact 1D derivations)
+    for v, target in ((1, 1 / 6), (0, 2 / 3), (-1, 1 / 6)):
+        assert abs(w[e[:, 0] == v].sum() - target) < 1e-15
+
+
+# ----------------------------------------------------------------------------------------------
+# pore-space clean-up vs scipy.ndimage.label (+ periodic merge)
+# ----------------------------------------------------------------------------------------------
+
+def _label_reference(lattice, solid):
+    from scipy import ndimage
+    nz, ny, nx = solid.shape
+    fluid = solid == 0
+    if lattice == "D2Q9":
+        lab, n = ndimage.label(fluid[0], structure=np.ones((3, 3)))
+        lab = lab[None]
+    else:
+        lab, n = ndimage.label(fluid, structure=ndimage.generate_binary_structure(3, 2))
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    def union(a, b):
+        if a and b:
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                parent[ra] = rb
+
+    e, _ = oracle.velocities(lattice)
+    # links that cross the periodic y / z seams
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                a = lab[z, y, x]
+                if not a:
+                    continue
+                for ex, ey, ez in e[1:]:
+                    xx, yy, zz = x + ex, y + ey, z + ez
+                    if not (0 <= xx < nx):
+                        continue
+                    if 0 <= yy < ny and 0 <= zz < nz:
+                        continue
+                    union(a, lab[zz % nz, yy % ny, xx])
+    roots_in = {find(l) for l in np.unique(lab[:, :, 0]) if l}
+    keep = np.zeros_like(fluid)
+    for l in range(1, n + 1):
+        if find(l) in roots_in:
+            keep |= lab == l
+    return (~keep).astype(np.uint8)
+
+
+@pytest.mark.parametrize("lat,shape,seed", [("D2Q9", (1, 40, 30), 1), ("D2Q9", (1, 25, 33), 2),
+                                            ("D3Q19", (9, 11, 13), 3)])
+def test_label_matches_scipy(lat, shape, seed):
+    rng = np.random.default_rng(seed)
+    solid = (rng.random(shape) < (0.55 if lat == "D2Q9" else 0.7)).astype(np.uint8)
+    got, n_open = oracle.label(lat, solid)
+    ref = _label_reference(lat, solid)
+    assert np.array_equal(got, ref)
+    assert n_open == int((ref[:, :, -1] == 0).sum())
+
+
+# ----------------------------------------------------------------------------------------------
+# closed forms
+# ----------------------------------------------------------------------------------------------
+
+def test_binary_linear_profile():
+    """X_3 = 0: D_1 = D_2 = D_12 is constant and the exact discrete steady state is linear,
+    X_1(k) = X_1,in - k Q / D*_12, with X(0) = X_in exactly (inlet rule) and slope set by the
+    imposed outlet flux."""
+    case = inputs.stefan_tube(nx=24, ny=1, tau_ref=1.5, X_in=(0.7, 0.3, 0.0))
+    q = 1.5e-3
+    o = oracle.Oracle(case, Q_override=(q, -q))
+    o.init_uniform()
+    X, _ = run_to_steady(o, window=5000, tol=1e-16)
+    Dl12 = o.lp["Dl"][0, 1]
+    k = np.arange(case.nx)
+    assert np.max(np.abs(X[0, 0, 0] - (0.7 - k * q / Dl12))) < 1e-12
+    assert np.max(np.abs(X[1, 0, 0] - (0.3 + k * q / Dl12))) < 1e-12
+
+
+@pytest.mark.parametrize("tau", [1.0, 3.0])
+def test_exact_variance_d2q9(tau):
+    """Gaussian pulse far from every boundary, constant tau (binary, stoichiometric ratio):
+    the per-axis second moment follows the exact lattice relation at every step."""
+    n = 160
+    case = inputs.stefan_tube(nx=n, ny=n, tau_ref=tau, X_in=(0.5, 0.5, 0.0), j_A_cm2=0.0)
+    o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+    yy, xx = np.meshgrid(np.arange(n) - n / 2, np.arange(n) - n / 2, indexing="ij")
+    s0 = 2.0
+    bump = 0.2 * np.exp(-(xx ** 2 + yy ** 2) / (2 * s0 ** 2))
+    X0 = _uniform(o, (0.5, 0.5, 0.0))
+    X0[0, 0] += bump
+    X0[1, 0] -= bump
+    o.init_field(X0)
+    dX = o.moments()[0, 0] - 0.5
+    M0 = dX.sum()
+    var0x = (dX * xx ** 2).sum() / M0
+    var0y = (dX * yy ** 2).sum() / M0
+    t = 0
+    for target in (1, 7, 40):
+        o.step(target - t)
+        t = target
+        dX = o.moments()[0, 0] - 0.5
+        assert abs(dX.sum() - M0) < 1e-13 * abs(M0) * 10
+        vx = (dX * xx ** 2).sum() / dX.sum()
+        vy = (dX * yy ** 2).sum() / dX.sum()
+        assert abs(vx - cf.exact_variance(var0x, tau, t)) < 1e-10 * vx
+        assert abs(vy - cf.exact_variance(var0y, tau, t)) < 1e-10 * vy
+
+
+def test_exact_variance_d3q19():
+    n = 40
+    tau = 1.0
+    case = inputs.stefan_tube(nx=n, ny=n, nz=n, lattice="D3Q19", tau_ref=tau,
+                              X_in=(0.5, 0.5, 0.0), j_A_cm2=0.0)
+    o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+    zz, yy, xx = np.meshgrid(*(np.arange(n) - n / 2,) * 3, indexing="ij")
+    s0 = 1.3
+    bump = 0.2 * np.exp(-(xx ** 2 + yy ** 2 + zz ** 2) / (2 * s0 ** 2))
+    X0 = _uniform(o, (0.5, 0.5, 0.0))
+    X0[0] += bump
+    X0[1] -= bump
+    o.init_field(X0)
+    dX = o.moments()[0] - 0.5
+    M0 = dX.sum()
+    v0 = [(dX * c ** 2).sum() / M0 for c in (xx, yy, zz)]
+    o.step(12)
+    dX = o.moments()[0] - 0.5
+    for c, v in zip((xx, yy, zz), v0):
+        got = (dX * c ** 2).sum() / dX.sum()
+        assert abs(got - cf.exact_variance(v, tau, 12)) < 1e-10 * got
+
+
+def test_stefan_chain_stoichiometric():
+    """Strongly coupled ternary tube (long tube, X_1 falls from 0.6 to ~0.3): the time-stepped
+    steady state equals the exact discrete chain solved by Newton's method."""
+    nx = 40
+    case = inputs.stefan_tube(nx=nx, ny=1, dx=0.1 / nx, tau_ref=5.0, j_A_cm2=0.5)
+    o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+    o.init_uniform()
+    X, _ = run_to_steady(o, window=4000)
+    chain = cf.discrete_chain_stoich(o.lp["Dl"], case.X_in, o.lp["Q"], nx)
+    assert X[0, 0, 0, -1] < 0.45  # the coupling is strong
+    assert np.max(np.abs(X[:2, 0, 0, :] - chain)) < 1e-12
+
+
+@pytest.mark.parametrize("mode", [oracle.LOCAL_FLUX, oracle.STOICH])
+def test_stefan_chain_identity(mode):
+    """Exact steady-state identity of the scheme with node-wise tau, whatever tau is: X(0) =
+    X_in, and X(k) - X(k+1) = Q (1/D*(k) + 1/D*(k+1)) / 2 with D* = (tau - 1/2)/3."""
+    nx = 32
+    case = inputs.stefan_tube(nx=nx, ny=1, dx=0.05 / nx, tau_ref=8.0, j_A_cm2=0.7)
+    o = oracle.Oracle(case, ms_mode=mode)
+    o.init_uniform()
+    X, _ = run_to_steady(o, window=4000)
+    _, tau, _, hits = o.collide()
+    assert hits == 0
+    Dst = (tau[:, 0, 0, :] - 0.5) / 3.0
+    Q = o.lp["Q"]
+    for s in range(2):
+        assert abs(X[s, 0, 0, 0] - case.X_in[s]) < 1e-14
+        lhs = X[s, 0, 0, :-1] - X[s, 0, 0, 1:]
+        rhs = Q[s] * 0.5 * (1.0 / Dst[s, :-1] + 1.0 / Dst[s, 1:])
+        assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+@pytest.mark.parametrize("mode", [oracle.LOCAL_FLUX, oracle.STOICH])
+def test_stefan_continuum_second_order(mode):
+    """Against the continuum Maxwell-Stefan solution (matrix exponential of Eq. 19): the error at
+    the last node falls at second order in dx."""
+    L = 0.05
+    errs = []
+    sizes = (12, 24, 48)
+    for P in sizes:
+        dx = L / (P - 1)
+        case = inputs.stefan_tube(nx=P, ny=1, dx=dx, tau_ref=10.0, j_A_cm2=0.7)
+        o = oracle.Oracle(case, ms_mode=mode)
+        o.init_field(np.ascontiguousarray(oracle.paper_profile(case, P).reshape(3, 1, 1, P)))
+        X, _ = run_to_steady(o, window=2000, tol=1e-14)
+        ref = cf.stefan_continuum(case.D_matrix(), case.T, case.p, case.X_in, o.lp["N"], [L])
+        errs.append(np.max(np.abs(X[:2, 0, 0, -1] - ref[:2, 0])))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert errs[-1] < 2e-4
+    assert min(orders) > 1.8, (errs, orders)
+
+
+# ----------------------------------------------------------------------------------------------
+# conservation
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9))])
+def test_closed_box_conserves(lat, shape):
+    nz, ny, nx = shape
+    case = inputs.random_small(nx, ny, nz, lat, seed=11, solid_frac=0.2, j_A_cm2=0.0)
+    o = oracle.Oracle(case, inlet_wall=True)
+    o.init_field(inputs.random_field(shape, seed=12))
+    M0 = o.inventory()
+    for _ in range(5):
+        o.step(60)
+        assert np.all(np.abs(o.inventory() - M0) < 1e-13 * M0)
+
+
+@pytest.mark.parametrize("lat,shape,mode", [("D2Q9", (1, 16, 20), oracle.LOCAL_FLUX),
+                                            ("D3Q19", (5, 6, 10), oracle.STOICH)])
+def test_open_mass_balance(lat, shape, mode):
+    """Every step: inventory change = inflow - outflow, and the outflow is Q_s per open node."""
+    nz, ny, nx = shape
+    case = inputs.random_small(nx, ny, nz, lat, seed=21, solid_frac=0.2, j_A_cm2=1.0,
+                               tau_ref=2.0)
+    o = oracle.Oracle(case, ms_mode=mode)
+    o.init_uniform()
+    o.step(30)
+    for _ in range(20):
+        M0 = o.inventory()
+        inflow, outflow, hits = o.step_stats()
+        M1 = o.inventory()
+        assert hits == 0
+        assert np.all(np.abs((M1 - M0) - (inflow - outflow)) < 1e-14 * M0.max())
+        assert np.allclose(outflow, o.lp["Q"] * o.n_open, rtol=1e-12, atol=1e-18)
+
+
+# ----------------------------------------------------------------------------------------------
+# invariants
+# ----------------------------------------------------------------------------------------------
+
+def test_zero_current_keeps_inlet_composition():
+    case = inputs.porous_2d(n=48, seed=0, j_A_cm2=0.0, tau_ref=3.0)
+    o = oracle.Oracle(case)
+    o.init_uniform()
+    o.step(200)
+    X = o.moments()
+    fl = o.fluid()
+    for s in range(3):
+        assert np.max(np.abs(X[s][fl] - case.X_in[s])) < 1e-15
+    assert abs(o.overpotential()) < 1e-15
+
+
+def test_mirror_and_translation_in_y():
+    case = inputs.random_small(12, 10, 1, "D2Q9", seed=31, solid_frac=0.2, tau_ref=2.0)
+    o = oracle.Oracle(case)
+    o.init_uniform()
+    o.step(150)
+    X = o.moments()
+    mir = inputs.random_small(12, 10, 1, "D2Q9", seed=31, solid_frac=0.2, tau_ref=2.0)
+    mir.solid = np.ascontiguousarray(case.solid[:, ::-1, :])
+    om = oracle.Oracle(mir)
+    om.init_uniform()
+    om.step(150)
+    assert np.max(np.abs(om.moments()[:, :, ::-1, :] - X)) < 1e-14
+    tr = inputs.random_small(12, 10, 1, "D2Q9", seed=31, solid_frac=0.2, tau_ref=2.0)
+    tr.solid = np.ascontiguousarray(np.roll(case.solid, 3, axis=1))
+    ot = oracle.Oracle(tr)
+    ot.init_uniform()
+    ot.step(150)
+    assert np.max(np.abs(np.roll(X, 3, axis=2) - ot.moments())) < 1e-14
+
+
+def test_d2q9_equals_d3q19_for_uniform_cross_section():
+    """y(-z)-uniform problems reduce both lattices to the same D1Q3 dynamics."""
+    c2 = inputs.stefan_tube(nx=20, ny=3, tau_ref=4.0, dx=0.02 / 20)
+    c3 = inputs.stefan_tube(nx=20, ny=3, nz=2, lattice="D3Q19", tau_ref=4.0, dx=0.02 / 20)
+    a = oracle.Oracle(c2)
+    b = oracle.Oracle(c3)
+    a.init_uniform()
+    b.init_uniform()
+    a.step(500)
+    b.step(500)
+    Xa = a.moments()[:, 0, 0, :]
+    Xb = b.moments()
+    for z in range(2):
+        for y in range(3):
+            assert np.max(np.abs(Xb[:, z, y, :] - Xa)) < 1e-13
+
+
+def test_species_swap():
+    """Relabelling H2 <-> H2O together with nu, D and X_in relabels the solution."""
+    base = inputs.random_small(10, 8, 1, "D2Q9", seed=41, solid_frac=0.15, tau_ref=3.0,
+                               X_in=(0.5, 0.3, 0.2))
+    sw = inputs.random_small(10, 8, 1, "D2Q9", seed=41, solid_frac=0.15, tau_ref=3.0,
+                             X_in=(0.3, 0.5, 0.2))
+    sw.nu = (1, -1, 0)
+    sw.D13, sw.D23 = base.D23, base.D13
+    a = oracle.Oracle(base)
+    b = oracle.Oracle(sw)
+    a.init_uniform()
+    b.init_uniform()
+    a.step(300)
+    b.step(300)
+    Xa, Xb = a.moments(), b.moments()
+    assert np.max(np.abs(Xa[0] - Xb[1])) < 1e-13
+    assert np.max(np.abs(Xa[1] - Xb[0])) < 1e-13
+
+
+# ----------------------------------------------------------------------------------------------
+# Maxwell-Stefan flux solve, overpotential, warm-start profile
+# ----------------------------------------------------------------------------------------------
+
+def test_fluxes_satisfy_eq19():
+    """The fluxes from [B] (Eq. 32) and Cramer's rule satisfy the Maxwell-Stefan relations
+    (Eq. 19) directly, at interior nodes where the central difference applies."""
+    shape = (1, 9, 11)
+    case = inputs.stefan_tube(nx=11, ny=9, tau_ref=3.0)
+    o = oracle.Oracle(case)
+    o.init_field(inputs.random_field(shape, seed=5, lo=0.1, hi=0.8))
+    X = o.moments()
+    _, _, J, _ = o.collide()
+    Dl = o.lp["Dl"]
+    for d, ax in ((0, 3), (1, 2)):
+        g = 0.5 * (np.roll(X, -1, axis=ax) - np.roll(X, 1, axis=ax))
+        r = cf.eq19_residual(Dl, X, g, J[:, d])
+        inner = r[:, 0, :, 1:-1]
+        assert np.max(np.abs(inner)) < 1e-15 * 1e3
+
+
+def test_overpotential_binary_profile():
+    case = inputs.stefan_tube(nx=24, ny=2, tau_ref=1.5, X_in=(0.7, 0.3, 0.0))
+    q = 1.0e-3
+    o = oracle.Oracle(case, Q_override=(q, -q))
+    o.init_uniform()
+    run_to_steady(o, window=5000, tol=1e-16)
+    Dl12 = o.lp["Dl"][0, 1]
+    x1 = 0.7 - 23 * q / Dl12
+    x2 = 0.3 + 23 * q / Dl12
+    eta = cf.overpotential(case.T, 2, case.X_in, (x1, x2))
+    assert eta > 0
+    assert abs(o.overpotential() - eta) < 1e-13
+
+
+def test_paper_profile_solves_generalized_fick():
+    case = inputs.stefan_tube(nx=64, ny=1, dx=0.1 / 64, j_A_cm2=1.0)
+    P = oracle.paper_profile(case, 64)
+    assert np.allclose(P[:, 0], case.X_in, atol=1e-15)
+    ref = cf.stefan_continuum(case.D_matrix(), case.T, case.p, case.X_in,
+                              oracle.lattice_params(case)["N"], np.arange(64) * case.dx)
+    assert np.max(np.abs(P - ref)) < 1e-12
