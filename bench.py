@@ -1,0 +1,196 @@
+"""Benchmark of the LBM / Maxwell-Stefan hot path on one MI355X.
+
+Workload (default): the 1024 x 1024 porous anode slice (overlapping disks, void fraction 0.40,
+seed 2), D2Q9, FP32 populations (FP64 Maxwell-Stefan solve and reductions), ternary
+H2-H2O-Ar, X_in ~ Dirichlet(6, 3, 1), j = 1 A/cm^2.  A step is one time step of the whole path
+(stream, boundaries, moments, gradients, Maxwell-Stefan solve, relaxation time, collision) over
+the slice; the residual reduction runs every --check-every steps inside the timed region and the
+overpotential once at its end, as in a steady solve.
+
+Prints one JSON line: species-MLUPS (fluid nodes x 2 evolved species x steps / s / 1e6) as the
+value, the step kernel's roofline (algorithmic bytes per launch over its mean duration from HIP
+events on the launch stream), and the FP64 CPU oracle's rate on a bounded sample of the same
+workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "species-MLUPS & HBM GB/s (% roofline); steady solves/s vs plain at 1e-8 residual"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per fluid-node update: each of Q populations of the 2 evolved species read
+# once and written once (pull scheme)
+BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16"): 72,
+                  ("D2Q9", "bf16"): 72, ("D3Q19", "fp64"): 608, ("D3Q19", "fp32"): 304,
+                  ("D3Q19", "fp16"): 152, ("D3Q19", "bf16"): 152}
+KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
+                  "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        rec = data.get(workload_key)
+        if not rec or rec.get("kernel_hash") != kernel_hash():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(case, steps: int):
+    """The FP64 CPU oracle as it stands, on `steps` steps of the same slice (bounded sample)."""
+    import oracle
+    o = oracle.Oracle(case)
+    o.init_uniform()
+    o.step(1)  # warm-up (allocations, page faults)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    n_fluid = int(o.fluid().sum())
+    return {"value": 2.0 * n_fluid * steps / dt / 1e6, "unit": "species-MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d steps of the same %dx%d slice (%d fluid nodes), FP64, single thread"
+                      % (steps, case.nx, case.ny, n_fluid)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
+    ap.add_argument("--shift", default="global", choices=["global", "node"])
+    ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d"])
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--chunk-z", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solver shards nothing across GPUs "
+              "(use --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1809_01600_amd import inputs, lbm_ms
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "porous_2d":
+        case = inputs.porous_2d()
+        desc = ("porous anode slice D2Q9 1024x1024, overlapping disks r~U[4,12], void fraction "
+                "0.40, seed 2, X_in~Dirichlet(6,3,1), j=1.0 A/cm^2")
+    else:
+        case = inputs.porous_3d()
+        desc = ("porous anode block D3Q19 256^3, overlapping spheres r~U[3,8], void fraction "
+                "~U[0.35,0.50], seed 3, X_in=(0.6,0.3,0.1), j=1.0 A/cm^2")
+    shift = lbm_ms.SHIFT_NODE if args.shift == "node" else lbm_ms.SHIFT_GLOBAL
+    s = lbm_ms.Solver(case, precision=args.precision, shift_mode=shift, tile_y=args.tile_y,
+                      chunk_z=args.chunk_z)
+    info = s.get_info()
+    n_fluid = int(info.n_fluid)
+    s.init()
+    s.step(args.warmup)
+    s.residual()
+    torch.cuda.synchronize()
+
+    # timed region: K steps with the residual check every check_every steps, then eta
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < K:
+        n = min(args.check_every, K - done)
+        s.step(n)
+        done += n
+        r = s.residual()
+    eta = s.overpotential()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # step kernel alone: HIP events on the launch stream around K back-to-back launches
+    kernel_ms = s.time_steps(K) / K
+    bytes_per_launch = BYTES_PER_NODE[(case.lattice, args.precision)] * n_fluid
+    if shift == lbm_ms.SHIFT_NODE:
+        bytes_per_launch += 16 * n_fluid
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    wl_key = "%s_%s_%s" % (args.workload, args.precision, args.shift)
+    traffic = measured_traffic(wl_key, kernel_hash())
+
+    ms_per_step = elapsed * 1e3 / K
+    value = 2.0 * n_fluid * K / elapsed / 1e6
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "species-MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else args.precision.replace("fp", "f"),
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "lattice": case.lattice,
+            "nx": case.nx, "ny": case.ny, "nz": case.nz,
+            "fluid_nodes": n_fluid,
+            "storage": args.precision + ("" if args.precision in ("fp32", "fp64") else "-" + args.shift + "-shift"),
+            "ms_solve": "fp64",
+            "tau_ref": case.tau_ref,
+            "check_every": args.check_every,
+            "tile": [64, int(info.tile_y), int(info.chunk_z)],
+            "node_mlups": round(n_fluid * K / elapsed / 1e6, 1),
+            "residual_at_end": r,
+            "eta_V": eta,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_step2d" if case.lattice == "D2Q9" else "k_step3d",
+            "kernel_us": round(kernel_ms * 1e3, 3),
+            "bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+    s.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,205 @@
+/*
+ * lbm_ms.h - C ABI of the MI355X (gfx950) library for the advection-diffusion lattice Boltzmann
+ * model coupled to the Maxwell-Stefan equations (Huang, Bao, Jiang, Zhang, arXiv 1809.01600).
+ *
+ * The problem is the paper's anode of Section 4.1: a porous voxel domain, x = diffusion direction,
+ * a Dirichlet (channel-side) inlet at x = 0, a reactive-flux outlet at the anode/electrolyte
+ * interface x = nx - 1, periodic in y and z.  Species 1 (H2) and 2 (H2O) carry populations; the
+ * inert species 3 (Ar) is the balance X_3 = 1 - X_1 - X_2 (the (n-1)-dimensional closure of
+ * Section 3.2).  One step is, per fluid node: pull-stream of the post-collision populations with
+ * half-way bounce-back on solid links (Section 3.3), the inlet and outlet rules, the moments, the
+ * gradients (Eq. 35 / Eq. 37 / central differences), the Maxwell-Stefan flux solve (Eq. 31-34,
+ * Gamma = I), the effective diffusivity (Eq. 24 with signed flux norms), the relaxation time
+ * (Eq. 25) and the BGK collision toward w_a X (Eq. 28-29).
+ *
+ * Conventions
+ *  - Every function returns an lbm_ms_status (0 = OK, < 0 = error) unless stated otherwise; no
+ *    C++ exception crosses the ABI.  After an error, lbm_ms_last_error() describes it.
+ *  - Device memory: the caller allocates one device buffer of lbm_ms_workspace_bytes() bytes and
+ *    owns it; the handle never frees it.  The handle owns only host metadata and a small pinned
+ *    host staging buffer.
+ *  - Ordering: every call is ordered on params.stream (a hipStream_t, NULL = legacy default
+ *    stream).  Calls that return host values synchronize that stream; lbm_ms_step does not.
+ *  - Threading: a handle is used from one host thread at a time.
+ *  - Units: SI at the ABI (T in K, p in Pa, D in m^2/s, dx in m, current density in A/m^2).
+ *  - Arrays: node index n = (z * ny + y) * nx + x (x fastest).  Field arrays are [3][N] float64
+ *    (species-major), population arrays [2][Q][N] float64.
+ */
+#ifndef LBM_MS_H
+#define LBM_MS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ms_s* lbm_ms_t;
+
+typedef enum {
+    LBM_MS_OK = 0,
+    LBM_MS_E_ARG = -1,          /* invalid argument (sizes, compositions, null pointers) */
+    LBM_MS_E_STATE = -2,        /* call out of order (e.g. step before set_geometry/init) */
+    LBM_MS_E_GEOM = -3,         /* no fluid path links the inlet column to the outlet column */
+    LBM_MS_E_HIP = -4,          /* HIP runtime error (message in lbm_ms_last_error) */
+    LBM_MS_E_DIVERGED = -5,     /* non-finite mole fraction found by a residual check */
+    LBM_MS_E_NOT_CONVERGED = -6,/* max_steps reached before the residual fell below tol */
+    LBM_MS_E_NEG_FRACTION = -7, /* a mole fraction below -1e-12 (limiting current exceeded) */
+    LBM_MS_E_NOMEM = -8,        /* workspace too small, or host allocation failed */
+    LBM_MS_E_TAU_CLAMP = -9     /* a relaxation time hit tau_min / tau_max since the last check */
+} lbm_ms_status;
+
+enum { LBM_MS_D2Q9 = 0, LBM_MS_D3Q19 = 1 };
+
+/* population storage (collision arithmetic is FP64 for LBM_MS_FP64, FP32 otherwise; the
+ * Maxwell-Stefan solve, residual, mass balance and overpotential are FP64 in every mode) */
+enum { LBM_MS_FP64 = 0, LBM_MS_FP32 = 1, LBM_MS_FP16 = 2, LBM_MS_BF16 = 3 };
+
+/* 16-bit storage holds f - w_a c: c = inlet composition (GLOBAL) or the node's own mole
+ * fraction, kept in an FP32 field (NODE) */
+enum { LBM_MS_SHIFT_GLOBAL = 0, LBM_MS_SHIFT_NODE = 1 };
+
+/* flux-norm ratio |N_j| / |N_i| in Eq. 24: from the local generalized-Fick fluxes (LOCAL_FLUX,
+ * the paper's reading) or fixed at the stoichiometric ratio |nu_j| / |nu_i| (STOICH) */
+enum { LBM_MS_LOCAL_FLUX = 0, LBM_MS_STOICH = 1 };
+
+/* x = 0 face: Dirichlet anti-bounce-back (Eq. 36) or a bounce-back wall (closed box) */
+enum { LBM_MS_INLET_DIRICHLET = 0, LBM_MS_INLET_WALL = 1 };
+
+typedef struct {
+    int lattice;          /* LBM_MS_D2Q9 or LBM_MS_D3Q19 */
+    int nx, ny, nz;       /* nodes; nz must be 1 for D2Q9; nx >= 2 */
+    double T;             /* K */
+    double p;             /* Pa; C_t = p / (R T), R = 8.3145 */
+    double D[9];          /* binary Maxwell-Stefan diffusivities D_ij [m^2/s], row-major 3x3,
+                             symmetric, diagonal ignored */
+    int nu[3];            /* stoichiometric coefficients (Eq. 39); need nu1 = -nu2 != 0, nu3 = 0 */
+    int n_electrons;      /* electrons per reaction (Eq. 39, Eq. 43) */
+    double dx;            /* lattice spacing [m] */
+    double tau_ref;       /* dt = (tau_ref - 1/2) dx^2 / (3 max D_ij): the fastest binary pair
+                             relaxes with tau_ref (c_s^2 = 1/3, Eq. 25) */
+    int precision;        /* LBM_MS_FP64 / FP32 / FP16 / BF16 */
+    int shift_mode;       /* LBM_MS_SHIFT_GLOBAL / NODE (16-bit storage only) */
+    int ms_mode;          /* LBM_MS_LOCAL_FLUX / LBM_MS_STOICH */
+    int inlet_mode;       /* LBM_MS_INLET_DIRICHLET / LBM_MS_INLET_WALL */
+    double eps_flux;      /* regularizer of the flux-norm ratio, lattice units; < 0 selects
+                             1e-2 * max|Q_s| + 1e-14 (set at lbm_ms_set_bc) */
+    double tau_min;       /* relaxation-time clamp; 0 selects 0.5 + 1e-9 */
+    double tau_max;       /* 0 selects 1e6 */
+    int tile_y;           /* launch shape (0 = default); see lbm_ms_tile_options */
+    int chunk_z;          /* D3Q19 planes per workgroup (0 = default) */
+    void* stream;         /* hipStream_t */
+} lbm_ms_params;
+
+typedef struct {
+    double dt;            /* physical time step [s] */
+    double Ct;            /* total molar concentration [mol/m^3] */
+    double Dl[9];         /* lattice diffusivities D*_ij = D_ij dt / dx^2 */
+    double Q[2];          /* lattice outflow per open outlet node per step, species 1 and 2 */
+    double eps_flux;      /* regularizer in use */
+    int64_t n_fluid;      /* fluid nodes after the connectivity clean-up */
+    int64_t n_open_outlet;/* fluid nodes of the outlet column */
+    int64_t steps;        /* steps taken since the last init */
+    int q;                /* velocities of the lattice */
+    int tile_x, tile_y, chunk_z; /* launch shape in use */
+    size_t workspace_bytes;
+} lbm_ms_info;
+
+/* Device bytes the caller must provide for these parameters (0 if the parameters are invalid). */
+size_t lbm_ms_workspace_bytes(const lbm_ms_params* params);
+
+/* Create a handle over caller-owned device memory d_workspace (at least
+ * lbm_ms_workspace_bytes bytes, 256-byte aligned).  *out is NULL on error. */
+int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, lbm_ms_t* out);
+
+/* Solid mask on the host, nx*ny*nz bytes (1 = solid).  Fluid that no chain of lattice links
+ * (periodic in y and z) connects to the inlet column becomes solid; E_GEOM when no fluid node of
+ * the outlet column remains.  The cleaned mask and the per-node link table go to the device.
+ * In LBM_MS_INLET_WALL mode the mask is used as given. */
+int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
+
+/* Cleaned mask (after set_geometry) copied to a host buffer of nx*ny*nz bytes. */
+int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host);
+
+/* Boundary data: inlet mole fractions X_in[3] (>= 0, sum 1 within 1e-12) for the Dirichlet rule
+ * (Eq. 36) and the current density j [A/m^2] (>= 0) of the electrode flux N_s = -nu_s j / (n F)
+ * (Eq. 39).  Per open outlet node the lattice flux is Q_s = N_s dt / (C_t dx) * (ny nz / open
+ * outlet nodes), so the outlet face carries the superficial current.  Call after set_geometry. */
+int lbm_ms_set_bc(lbm_ms_t h, const double X_in[3], double j_A_per_m2);
+
+/* Initial state f_a = w_a X0 (equilibrium).  X0 == NULL: uniform inlet composition.  Otherwise
+ * X0 holds [3][N] float64 mole fractions (species 3 is ignored), in host memory
+ * (x0_on_device = 0) or device memory (x0_on_device = 1).  Resets the step counter and the
+ * residual snapshot. */
+int lbm_ms_init(lbm_ms_t h, const double* X0, int x0_on_device);
+
+/* The paper's initial field (Section 4.1): along x the flux equals the electrode flux and the
+ * generalized Fick law (Eq. 31, Gamma = I) is integrated from the inlet composition; the 1D
+ * profile is copied over y and z.  Uses the superficial flux (no open-area scaling). */
+int lbm_ms_init_paper_profile(lbm_ms_t h);
+
+/* nsteps time steps, enqueued on the stream (asynchronous). */
+int lbm_ms_step(lbm_ms_t h, int64_t nsteps);
+
+/* nsteps steps bracketed by HIP events on the stream; *ms = elapsed milliseconds (synchronizes). */
+int lbm_ms_time_steps(lbm_ms_t h, int64_t nsteps, double* ms);
+
+/* Residual over the window since the previous snapshot (init or the last residual call):
+ * r = ||X^t - X^{t-K}||_2 / (K ||X^t||_2) over fluid nodes and species 1, 2, K = steps since
+ * the snapshot (FP64 accumulation).  Takes a new snapshot.  Returns E_DIVERGED for non-finite
+ * values, E_NEG_FRACTION for X < -1e-12, E_TAU_CLAMP if a relaxation time was clamped. */
+int lbm_ms_residual(lbm_ms_t h, double* residual);
+
+/* Step until the residual, checked every check_every steps, is below tol, or max_steps steps
+ * were taken (E_NOT_CONVERGED).  Error codes as lbm_ms_residual. */
+int lbm_ms_converge(lbm_ms_t h, double tol, int64_t max_steps, int check_every,
+                    int64_t* steps_taken, double* residual);
+
+/* Mean mole fractions over the open outlet-column nodes (X_out[3], FP64). */
+int lbm_ms_outlet_mean(lbm_ms_t h, double X_out[3]);
+
+/* Concentration overpotential (Eq. 43): eta = (R T / n F) ln(X1_in X2_out / (X1_out X2_in)),
+ * X_out = outlet_mean, in volts. */
+int lbm_ms_overpotential(lbm_ms_t h, double* eta_volts);
+
+/* Mole-fraction field of the current state.  X: [3][N] float64 in host memory (on_device = 0)
+ * or device memory (on_device = 1); solid nodes read 0. */
+int lbm_ms_get_fields(lbm_ms_t h, double* X, int on_device);
+
+/* Post-collision populations of the current state, decoded to float64, host [2][Q][N], in the
+ * velocity order of lbm_ms_lattice_info. */
+int lbm_ms_get_populations(lbm_ms_t h, double* f_host);
+
+/* Species inventory sum_r X_s (fluid nodes) of the current state, and the amounts that the next
+ * step moves in through the inlet face and out through the outlet face (species 1 and 2). */
+int lbm_ms_mass_balance(lbm_ms_t h, double inventory[2], double inflow[2], double outflow[2]);
+
+/* Checkpoint: *bytes = size when host_buf is NULL; otherwise writes the state (populations,
+ * node shift field, residual snapshot, step count, parameter hash) into host_buf. */
+int lbm_ms_save_state(lbm_ms_t h, void* host_buf, size_t* bytes);
+int lbm_ms_load_state(lbm_ms_t h, const void* host_buf, size_t bytes);
+
+int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info);
+
+/* Velocity set of a lattice: *q, e[3*q] (ex, ey, ez), w[q] (either pointer may be NULL). */
+int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w);
+
+/* Launch shapes compiled for a lattice: writes up to cap (tile_y, chunk_z) pairs, returns the
+ * count (chunk_z is 0 for D2Q9). */
+int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap);
+
+/* Change the launch shape of an existing handle (one of lbm_ms_tile_options). */
+int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z);
+
+const char* lbm_ms_last_error(lbm_ms_t h);
+const char* lbm_ms_status_string(int status);
+
+/* Release host resources; never frees the caller's workspace.  Synchronizes the stream. */
+void lbm_ms_destroy(lbm_ms_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_MS_H */

@@ -1,0 +1,25 @@
+// Host-side launchers of the HIP kernels (declarations shared by the runtime translation unit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_ms_device.hpp"
+
+namespace lbmms {
+
+int tile_options(int lattice, int* ty, int* cz, int cap);
+hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,
+                       int ty, int cz, int nblocks);
+hipError_t launch_init(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
+                       const double* X, double u0, double u1);
+hipError_t launch_residual(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
+                           double* snap, int update, double* partial, int nblocks, double* out);
+hipError_t launch_faces(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
+                        double* partial, int nblocks, double* out);
+hipError_t launch_fields(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns, double* X);
+hipError_t launch_populations(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
+                              int s, int q, double* out);
+hipError_t launch_paper_profile(hipStream_t st, const StepArgs& a, double Qs0, double Qs1,
+                                double* prof, double* X);
+
+}  // namespace lbmms

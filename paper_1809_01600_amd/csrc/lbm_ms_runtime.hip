@@ -1,0 +1,841 @@
+// Host runtime behind the C ABI of include/lbm_ms.h: handle state, workspace layout, the pore-space
+// clean-up and node descriptors, the physical-to-lattice conversion, the stepping loop and the
+// reductions.  Every per-node computation of the method runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_ms.h"
+#include "lbm_ms_kernels.hpp"
+
+using namespace lbmms;
+
+namespace {
+
+constexpr double R_GAS = 8.3145;    // J / (mol K)
+constexpr double FARADAY = 96485.0; // C / mol (Eq. 39)
+constexpr int RED_BLOCKS = 1024;    // per-block partials of the reductions
+constexpr uint64_t STATE_MAGIC = 0x314d534c42304c31ull;
+
+struct Layout {
+    size_t f[2], xn[2], desc, snap, field, part, prof, flags, scal, total;
+};
+
+int q_of(int lattice) { return lattice == LBM_MS_D2Q9 ? 9 : 19; }
+
+size_t elem_bytes(int prec)
+{
+    switch (prec) {
+    case LBM_MS_FP64: return 8;
+    case LBM_MS_FP32: return 4;
+    default: return 2;
+    }
+}
+
+bool node_shift(const lbm_ms_params& p)
+{
+    return (p.precision == LBM_MS_FP16 || p.precision == LBM_MS_BF16) &&
+           p.shift_mode == LBM_MS_SHIFT_NODE;
+}
+
+bool valid_params(const lbm_ms_params* p, std::string* why)
+{
+    auto fail = [&](const char* m) { if (why) *why = m; return false; };
+    if (!p) return fail("params is NULL");
+    if (p->lattice != LBM_MS_D2Q9 && p->lattice != LBM_MS_D3Q19) return fail("unknown lattice");
+    if (p->nx < 2 || p->ny < 1 || p->nz < 1) return fail("need nx >= 2, ny >= 1, nz >= 1");
+    if (p->lattice == LBM_MS_D2Q9 && p->nz != 1) return fail("D2Q9 needs nz == 1");
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    if (N > (1ll << 31)) return fail("domain too large (more than 2^31 nodes)");
+    if (p->precision < LBM_MS_FP64 || p->precision > LBM_MS_BF16) return fail("unknown precision");
+    if (p->shift_mode != LBM_MS_SHIFT_GLOBAL && p->shift_mode != LBM_MS_SHIFT_NODE)
+        return fail("unknown shift mode");
+    if (p->ms_mode != LBM_MS_LOCAL_FLUX && p->ms_mode != LBM_MS_STOICH) return fail("unknown ms_mode");
+    if (p->inlet_mode != LBM_MS_INLET_DIRICHLET && p->inlet_mode != LBM_MS_INLET_WALL)
+        return fail("unknown inlet mode");
+    if (!(p->T > 0) || !(p->p > 0) || !(p->dx > 0)) return fail("T, p, dx must be positive");
+    if (!(p->tau_ref > 0.5)) return fail("tau_ref must exceed 1/2");
+    const double d12 = p->D[1], d13 = p->D[2], d23 = p->D[5];
+    if (!(d12 > 0) || !(d13 > 0) || !(d23 > 0)) return fail("binary diffusivities must be positive");
+    if (p->D[3] != d12 || p->D[6] != d13 || p->D[7] != d23) return fail("D must be symmetric");
+    if (p->nu[2] != 0 || p->nu[0] == 0 || p->nu[0] != -p->nu[1])
+        return fail("need nu1 = -nu2 != 0 and nu3 = 0 (equimolar counter-diffusion)");
+    if (p->n_electrons <= 0) return fail("n_electrons must be positive");
+    return true;
+}
+
+Layout layout(const lbm_ms_params& p)
+{
+    Layout L{};
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    const int q = q_of(p.lattice);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t fb = 2ull * q * N * elem_bytes(p.precision);
+    L.f[0] = take(fb);
+    L.f[1] = take(fb);
+    const size_t xb = node_shift(p) ? 2ull * N * sizeof(float) : 0;
+    L.xn[0] = take(xb);
+    L.xn[1] = take(xb);
+    L.desc = take(N * sizeof(uint32_t));
+    L.snap = take(2ull * N * sizeof(double));
+    L.field = take(3ull * N * sizeof(double));
+    L.part = take((size_t)RED_BLOCKS * 8 * sizeof(double));
+    L.prof = take(2ull * p.nx * sizeof(double));
+    L.flags = take(64);
+    L.scal = take(64 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ms_s {
+    lbm_ms_params p{};
+    hipStream_t stream = nullptr;
+    Layout L{};
+    char* ws = nullptr;
+    int q = 9;
+    long long N = 0;
+    int cur = 0;
+    // host state
+    std::vector<uint8_t> mask;
+    long long n_fluid = 0, n_open = 0;
+    double dt = 0, Ct = 0, Dl[9] = {0}, Q[2] = {0, 0}, Qs[2] = {0, 0}, Xin[3] = {0, 0, 0};
+    double j = 0, eps = 0, tau_min = 0, tau_max = 0;
+    bool geom = false, bc = false, ready = false;
+    long long steps = 0, snap_step = 0;
+    int ty = 0, cz = 0;
+    double* pinned = nullptr;
+    std::string err;
+
+    int fail(int code, const char* fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip(hipError_t e, const char* what)
+    {
+        if (e == hipSuccess) return LBM_MS_OK;
+        return fail(LBM_MS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+    void* at(size_t off) { return ws + off; }
+    int prec() const { return p.precision; }
+    int ns() const { return node_shift(p) ? 1 : 0; }
+
+    StepArgs args(int in_buf) const
+    {
+        StepArgs a{};
+        a.fin = ws + L.f[in_buf];
+        a.fout = ws + L.f[1 - in_buf];
+        a.xin = node_shift(p) ? reinterpret_cast<const float*>(ws + L.xn[in_buf]) : nullptr;
+        a.xout = node_shift(p) ? reinterpret_cast<float*>(ws + L.xn[1 - in_buf]) : nullptr;
+        a.desc = reinterpret_cast<const uint32_t*>(ws + L.desc);
+        a.flags = reinterpret_cast<unsigned*>(ws + L.flags);
+        a.N = N;
+        a.nx = p.nx;
+        a.ny = p.ny;
+        a.nz = p.nz;
+        a.tiles_x = (p.nx + 63) / 64;
+        a.tiles_y = (p.ny + ty - 1) / ty;
+        a.chunks_z = (p.lattice == LBM_MS_D3Q19) ? (p.nz + cz - 1) / cz : 1;
+        a.iD12 = 1.0 / Dl[1];
+        a.iD13 = 1.0 / Dl[2];
+        a.iD23 = 1.0 / Dl[5];
+        a.Xin0 = Xin[0];
+        a.Xin1 = Xin[1];
+        a.Q0 = Q[0];
+        a.Q1 = Q[1];
+        a.eps0 = eps * std::fabs((double)p.nu[0]);
+        a.eps1 = eps * std::fabs((double)p.nu[1]);
+        const double s0 = p.nu[0] > 0 ? -1.0 : 1.0, s1 = p.nu[1] > 0 ? -1.0 : 1.0;
+        a.sgn12 = s0 * s1;
+        a.rst21 = std::fabs((double)p.nu[1]) / std::fabs((double)p.nu[0]);
+        a.rst12 = std::fabs((double)p.nu[0]) / std::fabs((double)p.nu[1]);
+        a.c0 = Xin[0];
+        a.c1 = Xin[1];
+        a.tau_min = tau_min;
+        a.tau_max = tau_max;
+        a.ms_mode = p.ms_mode;
+        a.inlet_wall = p.inlet_mode == LBM_MS_INLET_WALL ? 1 : 0;
+        return a;
+    }
+    int nblocks_step() const
+    {
+        const long long tx = (p.nx + 63) / 64, tyy = (p.ny + ty - 1) / ty;
+        const long long tz = (p.lattice == LBM_MS_D3Q19) ? (p.nz + cz - 1) / cz : 1;
+        return (int)(tx * tyy * tz);
+    }
+    int sync() { return hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+};
+
+// ---------------------------------------------------------------------------------------------
+// pore-space clean-up and node descriptors (host)
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct HostLattice {
+    int q;
+    int e[19][3];
+};
+
+HostLattice host_lattice(int lattice)
+{
+    HostLattice H{};
+    H.q = q_of(lattice);
+    for (int k = 0; k < H.q; ++k) {
+        if (lattice == LBM_MS_D2Q9) {
+            H.e[k][0] = D2Q9::ex[k];
+            H.e[k][1] = D2Q9::ey[k];
+            H.e[k][2] = 0;
+        } else {
+            H.e[k][0] = D3Q19::ex[k];
+            H.e[k][1] = D3Q19::ey[k];
+            H.e[k][2] = D3Q19::ez[k];
+        }
+    }
+    return H;
+}
+
+// Breadth-first search over lattice links from every fluid node of the inlet column; fluid that
+// is not reached becomes solid.  Returns the number of reached outlet-column nodes.
+long long clean_pores(const lbm_ms_params& p, std::vector<uint8_t>& solid)
+{
+    const HostLattice H = host_lattice(p.lattice);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long N = (long long)nx * ny * nz;
+    std::vector<uint8_t> seen(N, 0);
+    std::vector<long long> queue;
+    queue.reserve(N / 4 + 16);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const long long n = ((long long)z * ny + y) * nx;
+            if (!solid[n]) { seen[n] = 1; queue.push_back(n); }
+        }
+    for (size_t head = 0; head < queue.size(); ++head) {
+        const long long n = queue[head];
+        const int x = (int)(n % nx);
+        const int y = (int)((n / nx) % ny);
+        const int z = (int)(n / ((long long)nx * ny));
+        for (int k = 1; k < H.q; ++k) {
+            const int xx = x + H.e[k][0];
+            if (xx < 0 || xx >= nx) continue;
+            const int yy = (y + H.e[k][1] + ny) % ny;
+            const int zz = (z + H.e[k][2] + nz) % nz;
+            const long long m = ((long long)zz * ny + yy) * nx + xx;
+            if (!solid[m] && !seen[m]) { seen[m] = 1; queue.push_back(m); }
+        }
+    }
+    long long open = 0;
+    for (long long n = 0; n < N; ++n) {
+        solid[n] = seen[n] ? 0 : 1;
+        if (seen[n] && (n % nx) == nx - 1) ++open;
+    }
+    return open;
+}
+
+void build_descriptors(const lbm_ms_params& p, const std::vector<uint8_t>& solid,
+                       std::vector<uint32_t>& desc)
+{
+    const HostLattice H = host_lattice(p.lattice);
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const long long N = (long long)nx * ny * nz;
+    desc.assign(N, 0u);
+    auto fluid_at = [&](int x, int y, int z) -> bool {
+        if (x < 0 || x >= nx) return false;
+        y = (y % ny + ny) % ny;
+        z = (z % nz + nz) % nz;
+        return !solid[((long long)z * ny + y) * nx + x];
+    };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long long n = ((long long)z * ny + y) * nx + x;
+                if (solid[n]) continue;
+                uint32_t d = FLUID;
+                if (x == 0) d |= INLET;
+                if (x == nx - 1) d |= OUTLET;
+                for (int k = 1; k < H.q; ++k) {
+                    const int sx = x - H.e[k][0];
+                    if (sx < 0 || sx >= nx) continue;  // boundary links: handled by INLET/OUTLET
+                    if (!fluid_at(sx, y - H.e[k][1], z - H.e[k][2])) d |= 1u << k;
+                }
+                if (fluid_at(x - 1, y, z)) d |= NB_XM;
+                if (fluid_at(x + 1, y, z)) d |= NB_XP;
+                if (fluid_at(x, y - 1, z)) d |= NB_YM;
+                if (fluid_at(x, y + 1, z)) d |= NB_YP;
+                if (p.lattice == LBM_MS_D3Q19) {
+                    if (fluid_at(x, y, z - 1)) d |= NB_ZM;
+                    if (fluid_at(x, y, z + 1)) d |= NB_ZP;
+                }
+                desc[n] = d;
+            }
+}
+
+int default_tile_y(const lbm_ms_params& p)
+{
+    if (p.tile_y > 0) return p.tile_y;
+    if (p.lattice == LBM_MS_D2Q9) return p.ny >= 16 ? 16 : (p.ny >= 8 ? 8 : 4);
+    return p.precision == LBM_MS_FP64 ? 4 : 8;
+}
+
+int default_chunk_z(const lbm_ms_params& p)
+{
+    if (p.lattice == LBM_MS_D2Q9) return 0;
+    if (p.chunk_z > 0) return p.chunk_z;
+    return p.nz >= 128 ? 32 : 16;
+}
+
+bool tile_ok(int lattice, int ty, int cz)
+{
+    int tys[8], czs[8];
+    const int n = tile_options(lattice, tys, czs, 8);
+    for (int i = 0; i < n; ++i)
+        if (tys[i] == ty && czs[i] == cz) return true;
+    return false;
+}
+
+uint64_t param_hash(const lbm_ms_params& p)
+{
+    // FNV-1a over the fields that fix the state layout
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* d, size_t n) {
+        const unsigned char* c = (const unsigned char*)d;
+        for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    };
+    mix(&p.lattice, sizeof(int)); mix(&p.nx, sizeof(int)); mix(&p.ny, sizeof(int));
+    mix(&p.nz, sizeof(int)); mix(&p.precision, sizeof(int)); mix(&p.shift_mode, sizeof(int));
+    return h;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+size_t lbm_ms_workspace_bytes(const lbm_ms_params* params)
+{
+    if (!valid_params(params, nullptr)) return 0;
+    return layout(*params).total;
+}
+
+int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, lbm_ms_t* out)
+{
+    if (!out) return LBM_MS_E_ARG;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(params, &why)) return LBM_MS_E_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return LBM_MS_E_ARG;
+    const Layout L = layout(*params);
+    if (bytes < L.total) return LBM_MS_E_NOMEM;
+    lbm_ms_s* h = new (std::nothrow) lbm_ms_s();
+    if (!h) return LBM_MS_E_NOMEM;
+    h->p = *params;
+    h->stream = (hipStream_t)params->stream;
+    h->L = L;
+    h->ws = (char*)d_workspace;
+    h->q = q_of(params->lattice);
+    h->N = (long long)params->nx * params->ny * params->nz;
+    h->ty = default_tile_y(*params);
+    h->cz = default_chunk_z(*params);
+    if (!tile_ok(params->lattice, h->ty, h->cz)) { delete h; return LBM_MS_E_ARG; }
+    h->tau_min = params->tau_min > 0 ? params->tau_min : 0.5 + 1e-9;
+    h->tau_max = params->tau_max > 0 ? params->tau_max : 1e6;
+    // lattice units: dt from tau_ref for the fastest pair (Eq. 25 with c_s^2 = 1/3)
+    const double Dmax = std::max(params->D[1], std::max(params->D[2], params->D[5]));
+    h->dt = (params->tau_ref - 0.5) * params->dx * params->dx / (3.0 * Dmax);
+    for (int i = 0; i < 9; ++i) h->Dl[i] = params->D[i] * h->dt / (params->dx * params->dx);
+    h->Ct = params->p / (R_GAS * params->T);
+    if (hipHostMalloc((void**)&h->pinned, 4096) != hipSuccess) { delete h; return LBM_MS_E_HIP; }
+    // clear the flag words
+    if (hipMemsetAsync(h->at(L.flags), 0, 64, h->stream) != hipSuccess) {
+        hipHostFree(h->pinned);
+        delete h;
+        return LBM_MS_E_HIP;
+    }
+    *out = h;
+    return LBM_MS_OK;
+}
+
+void lbm_ms_destroy(lbm_ms_t h)
+{
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    if (h->pinned) hipHostFree(h->pinned);
+    delete h;
+}
+
+const char* lbm_ms_last_error(lbm_ms_t h) { return h ? h->err.c_str() : "null handle"; }
+
+const char* lbm_ms_status_string(int s)
+{
+    switch (s) {
+    case LBM_MS_OK: return "ok";
+    case LBM_MS_E_ARG: return "invalid argument";
+    case LBM_MS_E_STATE: return "call out of order";
+    case LBM_MS_E_GEOM: return "outlet not connected to the inlet";
+    case LBM_MS_E_HIP: return "HIP runtime error";
+    case LBM_MS_E_DIVERGED: return "non-finite mole fraction";
+    case LBM_MS_E_NOT_CONVERGED: return "not converged within max_steps";
+    case LBM_MS_E_NEG_FRACTION: return "negative mole fraction (limiting current exceeded)";
+    case LBM_MS_E_NOMEM: return "workspace too small or out of memory";
+    case LBM_MS_E_TAU_CLAMP: return "relaxation time clamped";
+    }
+    return "unknown status";
+}
+
+int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w)
+{
+    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
+    const int Q = q_of(lattice);
+    if (q) *q = Q;
+    for (int k = 0; k < Q; ++k) {
+        if (e) {
+            e[3 * k + 0] = lattice == 0 ? D2Q9::ex[k] : D3Q19::ex[k];
+            e[3 * k + 1] = lattice == 0 ? D2Q9::ey[k] : D3Q19::ey[k];
+            e[3 * k + 2] = lattice == 0 ? D2Q9::ez[k] : D3Q19::ez[k];
+        }
+        if (w) w[k] = lattice == 0 ? D2Q9::w[k] : D3Q19::w[k];
+    }
+    return LBM_MS_OK;
+}
+
+int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap)
+{
+    (void)precision;
+    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
+    return tile_options(lattice, tile_y, chunk_z, cap);
+}
+
+int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z)
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (h->p.lattice == LBM_MS_D2Q9) chunk_z = 0;
+    if (!tile_ok(h->p.lattice, tile_y, chunk_z))
+        return h->fail(LBM_MS_E_ARG, "launch shape (%d, %d) not compiled", tile_y, chunk_z);
+    h->ty = tile_y;
+    h->cz = chunk_z;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
+{
+    if (!h || !solid_host) return LBM_MS_E_ARG;
+    h->mask.assign(solid_host, solid_host + h->N);
+    for (auto& v : h->mask) v = v ? 1 : 0;
+    if (h->p.inlet_mode == LBM_MS_INLET_DIRICHLET) {
+        h->n_open = clean_pores(h->p, h->mask);
+        if (h->n_open <= 0) {
+            h->geom = false;
+            return h->fail(LBM_MS_E_GEOM, "no fluid path from the inlet column to the outlet column");
+        }
+    } else {
+        h->n_open = 0;
+        for (long long n = h->p.nx - 1; n < h->N; n += h->p.nx) h->n_open += h->mask[n] ? 0 : 1;
+    }
+    h->n_fluid = 0;
+    for (auto v : h->mask) h->n_fluid += v ? 0 : 1;
+    std::vector<uint32_t> desc;
+    build_descriptors(h->p, h->mask, desc);
+    int rc = h->hip(hipMemcpyAsync(h->at(h->L.desc), desc.data(), desc.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, h->stream), "descriptor upload");
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    h->geom = true;
+    h->ready = false;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host)
+{
+    if (!h || !solid_host) return LBM_MS_E_ARG;
+    if (!h->geom) return h->fail(LBM_MS_E_STATE, "set_geometry first");
+    std::memcpy(solid_host, h->mask.data(), h->N);
+    return LBM_MS_OK;
+}
+
+int lbm_ms_set_bc(lbm_ms_t h, const double X_in[3], double j)
+{
+    if (!h || !X_in) return LBM_MS_E_ARG;
+    if (!h->geom) return h->fail(LBM_MS_E_STATE, "set_geometry first");
+    for (int s = 0; s < 3; ++s)
+        if (!(X_in[s] >= 0.0)) return h->fail(LBM_MS_E_ARG, "X_in must be >= 0");
+    if (std::fabs(X_in[0] + X_in[1] + X_in[2] - 1.0) > 1e-12)
+        return h->fail(LBM_MS_E_ARG, "X_in must sum to 1");
+    if (!(j >= 0.0) || !std::isfinite(j)) return h->fail(LBM_MS_E_ARG, "j must be finite and >= 0");
+    for (int s = 0; s < 3; ++s) h->Xin[s] = X_in[s];
+    h->j = j;
+    // Eq. 39: N_s = -nu_s j / (n F); lattice flux per open outlet node
+    const double face = (double)h->p.ny * h->p.nz;
+    const double scale = h->n_open > 0 ? face / (double)h->n_open : 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const double Ns = -(double)h->p.nu[s] * j / (h->p.n_electrons * FARADAY);
+        h->Qs[s] = Ns * h->dt / (h->Ct * h->p.dx);
+        h->Q[s] = h->Qs[s] * scale;
+    }
+    h->eps = h->p.eps_flux >= 0 ? h->p.eps_flux
+                                : 1e-2 * std::max(std::fabs(h->Q[0]), std::fabs(h->Q[1])) + 1e-14;
+    h->bc = true;
+    return LBM_MS_OK;
+}
+
+static int init_common(lbm_ms_t h, const double* Xdev)
+{
+    h->cur = 0;
+    StepArgs a = h->args(1);  // writes buffer 0 (fout of in_buf = 1)
+    int rc = h->hip(launch_init(h->stream, a, h->p.lattice, h->prec(), h->ns(), Xdev, h->Xin[0],
+                                h->Xin[1]), "init kernel");
+    if (rc) return rc;
+    rc = h->hip(hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream), "flag reset");
+    if (rc) return rc;
+    // residual snapshot of the initial state
+    StepArgs r = h->args(0);
+    rc = h->hip(launch_residual(h->stream, r, h->p.lattice, h->prec(), h->ns(),
+                                (double*)h->at(h->L.snap), 1, (double*)h->at(h->L.part),
+                                RED_BLOCKS, (double*)h->at(h->L.scal)), "snapshot");
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    h->steps = 0;
+    h->snap_step = 0;
+    h->ready = true;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_init(lbm_ms_t h, const double* X0, int on_device)
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (!h->geom || !h->bc) return h->fail(LBM_MS_E_STATE, "set_geometry and set_bc first");
+    const double* Xdev = nullptr;
+    if (X0) {
+        if (on_device) {
+            Xdev = X0;
+        } else {
+            int rc = h->hip(hipMemcpyAsync(h->at(h->L.field), X0, 3ull * h->N * sizeof(double),
+                                           hipMemcpyHostToDevice, h->stream), "field upload");
+            if (rc) return rc;
+            Xdev = (const double*)h->at(h->L.field);
+        }
+    }
+    return init_common(h, Xdev);
+}
+
+int lbm_ms_init_paper_profile(lbm_ms_t h)
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (!h->geom || !h->bc) return h->fail(LBM_MS_E_STATE, "set_geometry and set_bc first");
+    StepArgs a = h->args(0);
+    int rc = h->hip(launch_paper_profile(h->stream, a, h->Qs[0], h->Qs[1], (double*)h->at(h->L.prof),
+                                         (double*)h->at(h->L.field)), "paper profile");
+    if (rc) return rc;
+    return init_common(h, (const double*)h->at(h->L.field));
+}
+
+int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    if (nsteps < 0) return h->fail(LBM_MS_E_ARG, "nsteps < 0");
+    const int nb = h->nblocks_step();
+    for (int64_t t = 0; t < nsteps; ++t) {
+        StepArgs a = h->args(h->cur);
+        hipError_t e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb);
+        if (e != hipSuccess) return h->hip(e, "step kernel");
+        h->cur ^= 1;
+        ++h->steps;
+    }
+    return LBM_MS_OK;
+}
+
+int lbm_ms_time_steps(lbm_ms_t h, int64_t nsteps, double* ms)
+{
+    if (!h || !ms) return LBM_MS_E_ARG;
+    hipEvent_t e0, e1;
+    int rc = h->hip(hipEventCreate(&e0), "event");
+    if (rc) return rc;
+    rc = h->hip(hipEventCreate(&e1), "event");
+    if (rc) { hipEventDestroy(e0); return rc; }
+    hipEventRecord(e0, h->stream);
+    rc = lbm_ms_step(h, nsteps);
+    hipEventRecord(e1, h->stream);
+    if (!rc) rc = h->hip(hipEventSynchronize(e1), "event sync");
+    float t = 0.f;
+    if (!rc) rc = h->hip(hipEventElapsedTime(&t, e0, e1), "elapsed");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = t;
+    return rc;
+}
+
+// runs the residual reduction; vals[0..5] as in k_residual
+static int reduce_state(lbm_ms_t h, int update, double* vals)
+{
+    StepArgs a = h->args(h->cur);
+    int rc = h->hip(launch_residual(h->stream, a, h->p.lattice, h->prec(), h->ns(),
+                                    (double*)h->at(h->L.snap), update, (double*)h->at(h->L.part),
+                                    RED_BLOCKS, (double*)h->at(h->L.scal)), "residual");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(h->pinned, h->at(h->L.scal), 8 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream), "residual readback");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(h->pinned + 8, h->at(h->L.flags), 16, hipMemcpyDeviceToHost,
+                               h->stream), "flag readback");
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    std::memcpy(vals, h->pinned, 6 * sizeof(double));
+    return LBM_MS_OK;
+}
+
+int lbm_ms_residual(lbm_ms_t h, double* residual)
+{
+    if (!h || !residual) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    double v[6];
+    int rc = reduce_state(h, 1, v);
+    if (rc) return rc;
+    const unsigned clamp = ((const unsigned*)(h->pinned + 8))[0];
+    const long long K = h->steps - h->snap_step;
+    h->snap_step = h->steps;
+    const double r = (K > 0 && v[1] > 0) ? std::sqrt(v[0]) / ((double)K * std::sqrt(v[1])) : 0.0;
+    *residual = r;
+    if (v[4] > 0 || !std::isfinite(r))
+        return h->fail(LBM_MS_E_DIVERGED, "%.0f nodes with non-finite mole fractions", v[4]);
+    if (v[5] > 0)
+        return h->fail(LBM_MS_E_NEG_FRACTION, "%.0f nodes with a mole fraction below -1e-12", v[5]);
+    if (clamp) {
+        hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream);
+        return h->fail(LBM_MS_E_TAU_CLAMP, "a relaxation time hit the clamp");
+    }
+    return LBM_MS_OK;
+}
+
+int lbm_ms_converge(lbm_ms_t h, double tol, int64_t max_steps, int check_every,
+                    int64_t* steps_taken, double* residual)
+{
+    if (!h || check_every <= 0 || max_steps < 0) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    // start a fresh window
+    double v[6];
+    int rc = reduce_state(h, 1, v);
+    if (rc) return rc;
+    h->snap_step = h->steps;
+    int64_t taken = 0;
+    double r = INFINITY;
+    while (taken < max_steps) {
+        const int64_t n = std::min<int64_t>(check_every, max_steps - taken);
+        rc = lbm_ms_step(h, n);
+        if (rc) break;
+        taken += n;
+        rc = lbm_ms_residual(h, &r);
+        if (rc) break;
+        if (r < tol) break;
+    }
+    if (steps_taken) *steps_taken = taken;
+    if (residual) *residual = r;
+    if (rc) return rc;
+    if (!(r < tol)) return h->fail(LBM_MS_E_NOT_CONVERGED, "residual %.3e after %lld steps", r, (long long)taken);
+    return LBM_MS_OK;
+}
+
+static int faces(lbm_ms_t h, double* v)
+{
+    StepArgs a = h->args(h->cur);
+    int rc = h->hip(launch_faces(h->stream, a, h->p.lattice, h->prec(), h->ns(), (double*)h->at(h->L.part),
+                                 RED_BLOCKS, (double*)h->at(h->L.scal) + 8), "face reduction");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(h->pinned, (double*)h->at(h->L.scal) + 8, 8 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream), "face readback");
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    std::memcpy(v, h->pinned, 7 * sizeof(double));
+    return LBM_MS_OK;
+}
+
+int lbm_ms_outlet_mean(lbm_ms_t h, double X_out[3])
+{
+    if (!h || !X_out) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    double v[7];
+    int rc = faces(h, v);
+    if (rc) return rc;
+    if (v[2] <= 0) return h->fail(LBM_MS_E_GEOM, "no open outlet node");
+    X_out[0] = v[0] / v[2];
+    X_out[1] = v[1] / v[2];
+    X_out[2] = 1.0 - X_out[0] - X_out[1];
+    return LBM_MS_OK;
+}
+
+int lbm_ms_overpotential(lbm_ms_t h, double* eta)
+{
+    if (!h || !eta) return LBM_MS_E_ARG;
+    double Xo[3];
+    int rc = lbm_ms_outlet_mean(h, Xo);
+    if (rc) return rc;
+    if (!(Xo[0] > 0 && Xo[1] > 0 && h->Xin[0] > 0 && h->Xin[1] > 0))
+        return h->fail(LBM_MS_E_NEG_FRACTION, "non-positive mole fraction in Eq. 43");
+    // Eq. 43
+    *eta = (R_GAS * h->p.T / (h->p.n_electrons * FARADAY)) *
+           std::log(h->Xin[0] * Xo[1] / (Xo[0] * h->Xin[1]));
+    return LBM_MS_OK;
+}
+
+int lbm_ms_mass_balance(lbm_ms_t h, double inventory[2], double inflow[2], double outflow[2])
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    double v[6], f[7];
+    int rc = reduce_state(h, 0, v);
+    if (rc) return rc;
+    rc = faces(h, f);
+    if (rc) return rc;
+    if (inventory) { inventory[0] = v[2]; inventory[1] = v[3]; }
+    if (inflow) { inflow[0] = f[3]; inflow[1] = f[4]; }
+    if (outflow) { outflow[0] = f[5]; outflow[1] = f[6]; }
+    return LBM_MS_OK;
+}
+
+int lbm_ms_get_fields(lbm_ms_t h, double* X, int on_device)
+{
+    if (!h || !X) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    StepArgs a = h->args(h->cur);
+    double* dst = on_device ? X : (double*)h->at(h->L.field);
+    int rc = h->hip(launch_fields(h->stream, a, h->p.lattice, h->prec(), h->ns(), dst), "fields");
+    if (rc) return rc;
+    if (!on_device) {
+        rc = h->hip(hipMemcpyAsync(X, dst, 3ull * h->N * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                    "field readback");
+        if (rc) return rc;
+    }
+    return h->sync();
+}
+
+int lbm_ms_get_populations(lbm_ms_t h, double* f)
+{
+    if (!h || !f) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    StepArgs a = h->args(h->cur);
+    double* tmp = (double*)h->at(h->L.field);
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < h->q; ++k) {
+            int rc = h->hip(launch_populations(h->stream, a, h->p.lattice, h->prec(), h->ns(), s, k, tmp),
+                            "populations");
+            if (rc) return rc;
+            rc = h->hip(hipMemcpyAsync(f + ((size_t)s * h->q + k) * h->N, tmp, h->N * sizeof(double),
+                                       hipMemcpyDeviceToHost, h->stream), "population readback");
+            if (rc) return rc;
+            rc = h->sync();
+            if (rc) return rc;
+        }
+    return LBM_MS_OK;
+}
+
+// checkpoint blob: header | populations | node shift field | residual snapshot
+struct StateHeader {
+    uint64_t magic, hash;
+    int64_t steps, snap_step;
+    uint64_t fbytes, xbytes, sbytes;
+};
+
+int lbm_ms_save_state(lbm_ms_t h, void* buf, size_t* bytes)
+{
+    if (!h || !bytes) return LBM_MS_E_ARG;
+    const size_t fb = 2ull * h->q * h->N * elem_bytes(h->p.precision);
+    const size_t xb = node_shift(h->p) ? 2ull * h->N * sizeof(float) : 0;
+    const size_t sb = 2ull * h->N * sizeof(double);
+    const size_t need = sizeof(StateHeader) + fb + xb + sb;
+    if (!buf) { *bytes = need; return LBM_MS_OK; }
+    if (*bytes < need) return h->fail(LBM_MS_E_ARG, "buffer too small (%zu < %zu)", *bytes, need);
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    StateHeader H{STATE_MAGIC, param_hash(h->p), h->steps, h->snap_step, fb, xb, sb};
+    char* c = (char*)buf;
+    std::memcpy(c, &H, sizeof(H));
+    c += sizeof(H);
+    int rc = h->hip(hipMemcpyAsync(c, h->at(h->L.f[h->cur]), fb, hipMemcpyDeviceToHost, h->stream), "save");
+    if (rc) return rc;
+    c += fb;
+    if (xb) {
+        rc = h->hip(hipMemcpyAsync(c, h->at(h->L.xn[h->cur]), xb, hipMemcpyDeviceToHost, h->stream), "save");
+        if (rc) return rc;
+        c += xb;
+    }
+    rc = h->hip(hipMemcpyAsync(c, h->at(h->L.snap), sb, hipMemcpyDeviceToHost, h->stream), "save");
+    if (rc) return rc;
+    *bytes = need;
+    return h->sync();
+}
+
+int lbm_ms_load_state(lbm_ms_t h, const void* buf, size_t bytes)
+{
+    if (!h || !buf) return LBM_MS_E_ARG;
+    if (!h->geom || !h->bc) return h->fail(LBM_MS_E_STATE, "set_geometry and set_bc first");
+    StateHeader H;
+    if (bytes < sizeof(H)) return h->fail(LBM_MS_E_ARG, "blob too small");
+    std::memcpy(&H, buf, sizeof(H));
+    const size_t fb = 2ull * h->q * h->N * elem_bytes(h->p.precision);
+    const size_t xb = node_shift(h->p) ? 2ull * h->N * sizeof(float) : 0;
+    const size_t sb = 2ull * h->N * sizeof(double);
+    if (H.magic != STATE_MAGIC || H.hash != param_hash(h->p) || H.fbytes != fb || H.xbytes != xb ||
+        H.sbytes != sb || bytes < sizeof(H) + fb + xb + sb)
+        return h->fail(LBM_MS_E_ARG, "checkpoint does not match this handle");
+    const char* c = (const char*)buf + sizeof(H);
+    h->cur = 0;
+    int rc = h->hip(hipMemcpyAsync(h->at(h->L.f[0]), c, fb, hipMemcpyHostToDevice, h->stream), "load");
+    if (rc) return rc;
+    c += fb;
+    if (xb) {
+        rc = h->hip(hipMemcpyAsync(h->at(h->L.xn[0]), c, xb, hipMemcpyHostToDevice, h->stream), "load");
+        if (rc) return rc;
+        c += xb;
+    }
+    rc = h->hip(hipMemcpyAsync(h->at(h->L.snap), c, sb, hipMemcpyHostToDevice, h->stream), "load");
+    if (rc) return rc;
+    rc = h->hip(hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream), "flag reset");
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    h->steps = H.steps;
+    h->snap_step = H.snap_step;
+    h->ready = true;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info)
+{
+    if (!h || !info) return LBM_MS_E_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->dt = h->dt;
+    info->Ct = h->Ct;
+    for (int i = 0; i < 9; ++i) info->Dl[i] = h->Dl[i];
+    info->Q[0] = h->Q[0];
+    info->Q[1] = h->Q[1];
+    info->eps_flux = h->eps;
+    info->n_fluid = h->n_fluid;
+    info->n_open_outlet = h->n_open;
+    info->steps = h->steps;
+    info->q = h->q;
+    info->tile_x = 64;
+    info->tile_y = h->ty;
+    info->chunk_z = h->cz;
+    info->workspace_bytes = h->L.total;
+    return LBM_MS_OK;
+}
+
+}  // extern "C"

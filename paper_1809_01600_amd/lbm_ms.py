@@ -1,0 +1,333 @@
+"""Thin ctypes binding of liblbm_ms.so (include/lbm_ms.h), same names as the C ABI.
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.  PyTorch
+provides the device workspace and the stream.  There is no fallback: if the shared library is
+missing or cannot be loaded, importing the binding's functions raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_ms.so")
+
+D2Q9, D3Q19 = 0, 1
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+SHIFT_GLOBAL, SHIFT_NODE = 0, 1
+LOCAL_FLUX, STOICH = 0, 1
+INLET_DIRICHLET, INLET_WALL = 0, 1
+
+OK = 0
+E_ARG, E_STATE, E_GEOM, E_HIP, E_DIVERGED = -1, -2, -3, -4, -5
+E_NOT_CONVERGED, E_NEG_FRACTION, E_NOMEM, E_TAU_CLAMP = -6, -7, -8, -9
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+
+
+class lbm_ms_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("T", ctypes.c_double), ("p", ctypes.c_double),
+        ("D", ctypes.c_double * 9),
+        ("nu", ctypes.c_int * 3),
+        ("n_electrons", ctypes.c_int),
+        ("dx", ctypes.c_double),
+        ("tau_ref", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("shift_mode", ctypes.c_int),
+        ("ms_mode", ctypes.c_int),
+        ("inlet_mode", ctypes.c_int),
+        ("eps_flux", ctypes.c_double),
+        ("tau_min", ctypes.c_double),
+        ("tau_max", ctypes.c_double),
+        ("tile_y", ctypes.c_int),
+        ("chunk_z", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class lbm_ms_info(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double),
+        ("Ct", ctypes.c_double),
+        ("Dl", ctypes.c_double * 9),
+        ("Q", ctypes.c_double * 2),
+        ("eps_flux", ctypes.c_double),
+        ("n_fluid", ctypes.c_int64),
+        ("n_open_outlet", ctypes.c_int64),
+        ("steps", ctypes.c_int64),
+        ("q", ctypes.c_int),
+        ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("chunk_z", ctypes.c_int),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class LbmMsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("lbm_ms status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol in include/lbm_ms.h
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_SIGNATURES = [
+    ("lbm_ms_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_ms_params)]),
+    ("lbm_ms_create", ctypes.c_int, [ctypes.POINTER(lbm_ms_params), _VP, ctypes.c_size_t,
+                                     ctypes.POINTER(_VP)]),
+    ("lbm_ms_set_geometry", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint8)]),
+    ("lbm_ms_get_geometry", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint8)]),
+    ("lbm_ms_set_bc", ctypes.c_int, [_VP, _DP, ctypes.c_double]),
+    ("lbm_ms_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    ("lbm_ms_init_paper_profile", ctypes.c_int, [_VP]),
+    ("lbm_ms_step", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("lbm_ms_time_steps", ctypes.c_int, [_VP, ctypes.c_int64, _DP]),
+    ("lbm_ms_residual", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_converge", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int64), _DP]),
+    ("lbm_ms_outlet_mean", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_overpotential", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_get_fields", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    ("lbm_ms_get_populations", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_mass_balance", ctypes.c_int, [_VP, _DP, _DP, _DP]),
+    ("lbm_ms_save_state", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_size_t)]),
+    ("lbm_ms_load_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
+    ("lbm_ms_get_info", ctypes.c_int, [_VP, ctypes.POINTER(lbm_ms_info)]),
+    ("lbm_ms_lattice_info", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), _DP]),
+    ("lbm_ms_tile_options", ctypes.c_int, [ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    ("lbm_ms_set_tile", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
+    ("lbm_ms_last_error", ctypes.c_char_p, [_VP]),
+    ("lbm_ms_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("lbm_ms_destroy", None, [_VP]),
+]
+
+SYMBOLS = [s[0] for s in _SIGNATURES]
+
+
+def lib():
+    """Load liblbm_ms.so (raises when it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblbm_ms.so is not built (run __graft_entry__.build() or "
+                              "python paper_1809_01600_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def lattice_info(lattice: int):
+    q = ctypes.c_int(0)
+    lib().lbm_ms_lattice_info(lattice, ctypes.byref(q), None, None)
+    e = np.zeros(3 * q.value, dtype=np.int32)
+    w = np.zeros(q.value)
+    lib().lbm_ms_lattice_info(lattice, ctypes.byref(q),
+                              e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w))
+    return e.reshape(q.value, 3), w
+
+
+def tile_options(lattice: int, precision: int = FP32):
+    ty = (ctypes.c_int * 16)()
+    cz = (ctypes.c_int * 16)()
+    n = lib().lbm_ms_tile_options(lattice, precision, ty, cz, 16)
+    return [(ty[i], cz[i]) for i in range(n)]
+
+
+def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
+                ms_mode: int = LOCAL_FLUX, inlet_mode: int = INLET_DIRICHLET,
+                eps_flux: float = -1.0, tau_min: float = 0.0, tau_max: float = 0.0,
+                tile_y: int = 0, chunk_z: int = 0, stream: Optional[int] = None) -> lbm_ms_params:
+    """Marshal a physical problem description (inputs.Case) into lbm_ms_params."""
+    p = lbm_ms_params()
+    p.lattice = D2Q9 if case.lattice == "D2Q9" else D3Q19
+    p.nx, p.ny, p.nz = case.nx, case.ny, case.nz
+    p.T, p.p = case.T, case.p
+    D = case.D_matrix().reshape(-1)
+    for i in range(9):
+        p.D[i] = float(D[i])
+    for s in range(3):
+        p.nu[s] = int(case.nu[s])
+    p.n_electrons = case.n_electrons
+    p.dx = case.dx
+    p.tau_ref = case.tau_ref
+    p.precision = precision
+    p.shift_mode = shift_mode
+    p.ms_mode = ms_mode
+    p.inlet_mode = inlet_mode
+    p.eps_flux = eps_flux
+    p.tau_min, p.tau_max = tau_min, tau_max
+    p.tile_y, p.chunk_z = tile_y, chunk_z
+    p.stream = stream
+    return p
+
+
+class Solver:
+    """One problem on one GPU: a handle plus its torch-owned device workspace."""
+
+    def __init__(self, case, precision="fp64", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
+                 inlet_mode=INLET_DIRICHLET, eps_flux=-1.0, tau_min=0.0, tau_max=0.0,
+                 tile_y=0, chunk_z=0, device="cuda", set_geometry=True, set_bc=True):
+        import torch
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.case = case
+        self.torch_device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.torch_device)
+        self.params = make_params(case, precision, shift_mode, ms_mode, inlet_mode, eps_flux,
+                                  tau_min, tau_max, tile_y, chunk_z, self.stream.cuda_stream)
+        nbytes = lib().lbm_ms_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise LbmMsError(E_ARG, "invalid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.torch_device)
+        h = _VP()
+        self._check(lib().lbm_ms_create(ctypes.byref(self.params),
+                                        ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                        ctypes.byref(h)), handle=False)
+        self.h = h
+        self.N = case.nx * case.ny * case.nz
+        self.q = 9 if case.lattice == "D2Q9" else 19
+        if set_geometry:
+            self.set_geometry(case.mask())
+            if set_bc:
+                self.set_bc(case.X_in, case.j_A_m2)
+
+    # -- plumbing ------------------------------------------------------------------------------
+    def _check(self, rc: int, handle: bool = True):
+        if rc != OK:
+            msg = lib().lbm_ms_status_string(rc).decode()
+            if handle and getattr(self, "h", None):
+                msg += ": " + lib().lbm_ms_last_error(self.h).decode()
+            raise LbmMsError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_ms_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI, same names -------------------------------------------------------------------
+    def set_geometry(self, solid: np.ndarray):
+        solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
+        if solid.size != self.N:
+            raise ValueError("mask has %d entries, expected %d" % (solid.size, self.N))
+        self._check(lib().lbm_ms_set_geometry(
+            self.h, solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+    def get_geometry(self) -> np.ndarray:
+        out = np.empty(self.N, dtype=np.uint8)
+        self._check(lib().lbm_ms_get_geometry(self.h,
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.reshape(self.case.shape)
+
+    def set_bc(self, X_in: Sequence[float], j_A_m2: float):
+        x = np.ascontiguousarray(X_in, dtype=np.float64)
+        self._check(lib().lbm_ms_set_bc(self.h, _dp(x), float(j_A_m2)))
+
+    def init(self, X0=None):
+        """X0: None (uniform inlet composition), numpy [3, ...] (host) or torch tensor (device)."""
+        if X0 is None:
+            self._check(lib().lbm_ms_init(self.h, None, 0))
+        elif hasattr(X0, "data_ptr"):
+            assert X0.dtype.is_floating_point and X0.numel() == 3 * self.N and X0.is_contiguous()
+            self._check(lib().lbm_ms_init(self.h, ctypes.c_void_p(X0.data_ptr()), 1))
+        else:
+            a = np.ascontiguousarray(X0, dtype=np.float64).reshape(-1)
+            assert a.size == 3 * self.N
+            self._check(lib().lbm_ms_init(self.h, a.ctypes.data_as(_VP), 0))
+
+    def init_paper_profile(self):
+        self._check(lib().lbm_ms_init_paper_profile(self.h))
+
+    def step(self, n: int = 1):
+        self._check(lib().lbm_ms_step(self.h, int(n)))
+
+    def time_steps(self, n: int) -> float:
+        ms = ctypes.c_double(0.0)
+        self._check(lib().lbm_ms_time_steps(self.h, int(n), ctypes.byref(ms)))
+        return ms.value
+
+    def residual(self) -> float:
+        r = ctypes.c_double(0.0)
+        self._check(lib().lbm_ms_residual(self.h, ctypes.byref(r)))
+        return r.value
+
+    def converge(self, tol: float, max_steps: int, check_every: int = 100):
+        steps = ctypes.c_int64(0)
+        r = ctypes.c_double(0.0)
+        rc = lib().lbm_ms_converge(self.h, tol, int(max_steps), int(check_every),
+                                   ctypes.byref(steps), ctypes.byref(r))
+        self._check(rc)
+        return steps.value, r.value
+
+    def outlet_mean(self) -> np.ndarray:
+        x = np.zeros(3)
+        self._check(lib().lbm_ms_outlet_mean(self.h, _dp(x)))
+        return x
+
+    def overpotential(self) -> float:
+        e = ctypes.c_double(0.0)
+        self._check(lib().lbm_ms_overpotential(self.h, ctypes.byref(e)))
+        return e.value
+
+    def get_fields(self, out=None) -> np.ndarray:
+        """[3, nz, ny, nx] float64 on the host, or into a contiguous float64 torch tensor."""
+        if out is not None:
+            self._check(lib().lbm_ms_get_fields(self.h, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        X = np.empty(3 * self.N)
+        self._check(lib().lbm_ms_get_fields(self.h, X.ctypes.data_as(_VP), 0))
+        return X.reshape((3,) + self.case.shape)
+
+    def get_populations(self) -> np.ndarray:
+        f = np.empty(2 * self.q * self.N)
+        self._check(lib().lbm_ms_get_populations(self.h, _dp(f)))
+        return f.reshape((2, self.q) + self.case.shape)
+
+    def mass_balance(self):
+        inv, inf, outf = np.zeros(2), np.zeros(2), np.zeros(2)
+        self._check(lib().lbm_ms_mass_balance(self.h, _dp(inv), _dp(inf), _dp(outf)))
+        return inv, inf, outf
+
+    def save_state(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self._check(lib().lbm_ms_save_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().lbm_ms_save_state(self.h, ctypes.cast(buf, _VP), ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(lib().lbm_ms_load_state(self.h, ctypes.cast(buf, _VP), len(blob)))
+
+    def get_info(self) -> lbm_ms_info:
+        info = lbm_ms_info()
+        self._check(lib().lbm_ms_get_info(self.h, ctypes.byref(info)))
+        return info
+
+    def set_tile(self, tile_y: int, chunk_z: int = 0):
+        self._check(lib().lbm_ms_set_tile(self.h, tile_y, chunk_z))

@@ -1,0 +1,79 @@
+"""The C ABI library loads and exports every declared symbol (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01600_amd import inputs, lbm_ms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm_ms.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_ms_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = lbm_ms.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm_ms.SYMBOLS)
+
+
+def test_lattice_tables_match_the_oracle_as_sets():
+    for lat, name in ((lbm_ms.D2Q9, "D2Q9"), (lbm_ms.D3Q19, "D3Q19")):
+        e, w = lbm_ms.lattice_info(lat)
+        eo, wo = oracle.velocities(name)
+        a = sorted((tuple(v), round(x, 15)) for v, x in zip(e.tolist(), w))
+        b = sorted((tuple(v), round(x, 15)) for v, x in zip(eo.tolist(), wo))
+        assert a == b
+        # opposite vectors exist
+        for v in e.tolist():
+            assert [-c for c in v] in e.tolist()
+
+
+def test_d2q9_order_is_the_papers():
+    e, w = lbm_ms.lattice_info(lbm_ms.D2Q9)
+    eo, _ = oracle.velocities("D2Q9")
+    assert np.array_equal(e, eo)
+
+
+def test_workspace_bytes_and_validation():
+    case = inputs.stefan_tube()
+    p = lbm_ms.make_params(case, precision=lbm_ms.FP32)
+    n32 = lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(p))
+    p64 = lbm_ms.make_params(case, precision=lbm_ms.FP64)
+    n64 = lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(p64))
+    N = case.nx * case.ny
+    assert n64 - n32 >= 2 * (2 * 9 * N * 4) - 4096
+    bad = lbm_ms.make_params(case)
+    bad.nx = 1
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = lbm_ms.make_params(case)
+    bad.nu[2] = 1
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = lbm_ms.make_params(case)
+    bad.nz = 2
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_tile_options_and_status_strings():
+    assert (16, 0) in lbm_ms.tile_options(lbm_ms.D2Q9)
+    assert all(cz > 0 for _, cz in lbm_ms.tile_options(lbm_ms.D3Q19))
+    for code in range(-9, 1):
+        assert lbm_ms.lib().lbm_ms_status_string(code).decode() != "unknown status"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(lbm_ms, "_lib", None)
+    monkeypatch.setattr(lbm_ms, "LIB_PATH", "/nonexistent/liblbm_ms.so")
+    with pytest.raises(ImportError):
+        lbm_ms.lib()
