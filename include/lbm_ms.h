@@ -115,7 +115,7 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
 
 /* Solid mask on the host, nx*ny*nz bytes (1 = solid).  Fluid that no chain of lattice links
  * (periodic in y and z) connects to the inlet column becomes solid; E_GEOM when no fluid node of
- * the outlet column remains.  The cleaned mask and the per-node link table go to the device.
+ * the outlet column remains.  The fluid index map of the cleaned mask goes to the device.
  * In LBM_MS_INLET_WALL mode the mask is used as given. */
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
 

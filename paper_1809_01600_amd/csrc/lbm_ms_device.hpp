@@ -9,18 +9,14 @@
 namespace lbmms {
 
 // ---------------------------------------------------------------------------------------------
-// node descriptor bits (one uint32 per node, built on the host from the cleaned mask)
+// neighbour bits returned by the pull (which axis neighbours exist and are fluid)
 // ---------------------------------------------------------------------------------------------
-constexpr uint32_t BB_MASK = (1u << 19) - 1;  // bit a: the pull source of link a is solid
-constexpr uint32_t NB_XM = 1u << 19;          // neighbour x-1 exists and is fluid
-constexpr uint32_t NB_XP = 1u << 20;          // neighbour x+1 exists and is fluid
-constexpr uint32_t NB_YM = 1u << 21;          // neighbour y-1 (periodic) is fluid
-constexpr uint32_t NB_YP = 1u << 22;
-constexpr uint32_t NB_ZM = 1u << 23;
-constexpr uint32_t NB_ZP = 1u << 24;
-constexpr uint32_t FLUID = 1u << 28;
-constexpr uint32_t INLET = 1u << 29;          // x == 0
-constexpr uint32_t OUTLET = 1u << 30;         // x == nx - 1
+constexpr uint32_t NB_XM = 1u << 0;  // x - 1
+constexpr uint32_t NB_XP = 1u << 1;  // x + 1
+constexpr uint32_t NB_YM = 1u << 2;  // y - 1 (periodic)
+constexpr uint32_t NB_YP = 1u << 3;
+constexpr uint32_t NB_ZM = 1u << 4;  // z - 1 (periodic)
+constexpr uint32_t NB_ZP = 1u << 5;
 
 // ---------------------------------------------------------------------------------------------
 // velocity sets
@@ -92,16 +88,35 @@ template <> struct Codec<P_BF16> {
 };
 
 // ---------------------------------------------------------------------------------------------
+// global-memory accessors: uniform base pointer + 32-bit byte offset (global_load/store with an
+// SGPR base and a VGPR offset; the pointers come from an in-memory table, so without the explicit
+// address space the compiler would fall back to flat accesses)
+// ---------------------------------------------------------------------------------------------
+#define LBMMS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ inline T gload(const void* base, unsigned byte_off)
+{
+    return *(const LBMMS_GLOBAL T*)((const LBMMS_GLOBAL char*)base + byte_off);
+}
+template <class T>
+__device__ inline void gstore(void* base, unsigned byte_off, T v)
+{
+    *(LBMMS_GLOBAL T*)((LBMMS_GLOBAL char*)base + byte_off) = v;
+}
+
+// ---------------------------------------------------------------------------------------------
 // per-launch arguments
 // ---------------------------------------------------------------------------------------------
 struct StepArgs {
-    const void* fin;          // post-collision populations of step t   [2][Q][N]
-    void* fout;               // post-collision populations of step t+1 [2][Q][N]
-    const float* xin;         // node shift field of step t   [2][N] (NODE shift only)
-    float* xout;              // node shift field of step t+1 [2][N]
-    const uint32_t* desc;     // node descriptors [N]
+    const void* fin;          // post-collision populations of step t   [2][Q][P] (fluid nodes)
+    void* fout;               // post-collision populations of step t+1 [2][Q][P]
+    const float* xin;         // node shift field of step t   [2][NF] (NODE shift only)
+    float* xout;              // node shift field of step t+1 [2][NF]
+    const int* idx;           // dense [N]: compact fluid index of the node, -1 for solid
     unsigned* flags;          // [0]: relaxation time clamped
-    long long N;
+    long long N;              // nodes of the box
+    long long NF;             // fluid nodes
+    long long P;              // elements between consecutive (species, link) planes (>= NF)
     int nx, ny, nz;
     int tiles_x, tiles_y, chunks_z;
     double iD12, iD13, iD23;  // 1 / D*_ij (lattice units)
@@ -111,7 +126,7 @@ struct StepArgs {
     double sgn12;             // sigma_1 * sigma_2, sigma_i = -sgn(nu_i) (Eq. 24 sign rule)
     double rst21, rst12;      // stoichiometric ratios |nu_2|/|nu_1|, |nu_1|/|nu_2|
     double c0, c1;            // global shift composition (16-bit GLOBAL storage)
-    double tau_min, tau_max;
+    double om_lo, om_hi;      // 1 / tau_max, 1 / tau_min (relaxation-time clamp)
     int ms_mode;              // 0 local flux norms, 1 stoichiometric ratio
     int inlet_wall;           // 1: x = 0 face is a bounce-back wall
 };
@@ -128,60 +143,96 @@ __device__ inline int xcd_tile(int b, int nb)
 // ---------------------------------------------------------------------------------------------
 // pull-stream of one fluid node with bounce-back and the x-boundary rules
 // ---------------------------------------------------------------------------------------------
-// Returns the post-stream populations f[s][a] of node n = (x, y, z) and their moments X0, X1
-// (FP64 sums).  Source of link a is r - e_a.  Links whose source is solid bounce back
+// Source of link a is r - e_a (periodic in y and z).  Links whose source is solid bounce back
 // (f_a(r) = f*_abar(r)); at the outlet column the links from x = nx take the exact-flux rule
 // f_a = f*_abar - (w_abar / W_out) Q_s; at the inlet column the links from x = -1 take
 // f_a = (w_a + w_abar) X_in - f_abar (Eq. 36) with f_abar the value just pulled, or bounce back
 // when the inlet is a wall.
-template <class L, int P, bool NS>
-__device__ inline void pull_node(const StepArgs& a, int x, int y, int z, long long n, uint32_t d,
-                                 typename Codec<P>::CT (&f)[2][L::Q], double& X0, double& X1)
+//
+// Source slots: si[a] = compact index of the source node, -1 if it is solid, BOUNDARY for the
+// links that cross the inlet or outlet face.
+constexpr int BOUNDARY = -3;
+
+// neighbour bit of an axis link whose source is fluid
+template <class L>
+__device__ inline uint32_t axis_bit(int k, int s)
 {
-    using C = Codec<P>;
-    using CT = typename C::CT;
-    using raw = typename C::raw;
-    const raw* __restrict__ fin = static_cast<const raw*>(a.fin);
-    const long long N = a.N;
+    const int ex = L::ex[k], ey = L::ey[k], ez = L::ez[k];
+    if (s < 0) return 0u;
+    if (ey == 0 && ez == 0 && ex != 0) return ex == 1 ? NB_XM : NB_XP;
+    if (ex == 0 && ez == 0 && ey != 0) return ey == 1 ? NB_YM : NB_YP;
+    if (ex == 0 && ey == 0 && ez != 0) return ez == 1 ? NB_ZM : NB_ZP;
+    return 0u;
+}
+
+// Source slots from the dense index map in global memory.
+template <class L>
+__device__ inline uint32_t global_sources(const StepArgs& a, int x, int y, int z, long long n, int i,
+                                          int (&si)[L::Q])
+{
     const long long nx = a.nx;
     const long long plane = nx * a.ny;
-    // offsets of the y / z neighbours, periodic
     const long long oym = (y > 0) ? -nx : (long long)(a.ny - 1) * nx;
     const long long oyp = (y < a.ny - 1) ? nx : -(long long)(a.ny - 1) * nx;
     const long long ozm = (z > 0) ? -plane : (long long)(a.nz - 1) * plane;
     const long long ozp = (z < a.nz - 1) ? plane : -(long long)(a.nz - 1) * plane;
-    const bool inlet = (d & INLET) != 0;
-    const bool outlet = (d & OUTLET) != 0;
-
-    float sh_own0 = 0.f, sh_own1 = 0.f;
-    if constexpr (NS) {
-        sh_own0 = a.xin[n];
-        sh_own1 = a.xin[N + n];
-    }
-    const float cg0 = (float)a.c0, cg1 = (float)a.c1;
-
+    uint32_t nb = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const int ex = L::ex[k], ey = L::ey[k], ez = L::ez[k];
-        const bool from_out = (ex == -1) && outlet;  // source at x = nx
-        const bool from_in = (ex == 1) && inlet;     // source at x = -1
-        const bool reflect = ((d >> k) & 1u) || from_out || (from_in && a.inlet_wall);
+        if (k == 0) { si[k] = i; continue; }
+        if ((ex == -1 && x == a.nx - 1) || (ex == 1 && x == 0)) { si[k] = BOUNDARY; continue; }
         long long src = n - ex;
         if (ey == 1) src += oym;
         if (ey == -1) src += oyp;
         if (ez == 1) src += ozm;
         if (ez == -1) src += ozp;
-        if (from_in) src = n;  // placeholder, replaced below (keeps the address valid)
-        const int kk = reflect ? L::opp[k] : k;
-        const long long m = reflect ? n : src;
-        const raw r0 = fin[(long long)kk * N + m];
-        const raw r1 = fin[(long long)(L::Q + kk) * N + m];
+        si[k] = gload<int>(a.idx, (unsigned)src * 4u);
+        nb |= axis_bit<L>(k, si[k]);
+    }
+    return nb;
+}
+
+// Branch-free gather of the post-stream populations of compact node i from its source slots,
+// then the inlet rule and the moments.  A lane with nothing to do passes i = 0 and zero slots.
+template <class L, int P, bool NS>
+__device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                              bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
+                              double& X1)
+{
+    using C = Codec<P>;
+    using CT = typename C::CT;
+    using raw = typename C::raw;
+    constexpr unsigned ES = sizeof(raw);
+    const void* fin = a.fin;
+    const unsigned plane = (unsigned)a.P * ES;          // bytes per (species, link) plane
+    const unsigned spec = (unsigned)L::Q * plane;       // bytes per species
+    const unsigned xsp = (unsigned)a.NF * 4u;           // bytes per species of the shift field
+    float sh_own0 = 0.f, sh_own1 = 0.f;
+    if constexpr (NS) {
+        sh_own0 = gload<float>(a.xin, (unsigned)i * 4u);
+        sh_own1 = gload<float>(a.xin, (unsigned)i * 4u + xsp);
+    }
+    const float cg0 = (float)a.c0, cg1 = (float)a.c1;
+    const bool wall = a.inlet_wall != 0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const int ex = L::ex[k];
+        const bool from_out = (ex == -1) && outlet;
+        const bool from_in = (ex == 1) && inlet;
+        const int s = si[k];
+        const bool local = (s < 0) || from_out || from_in;  // read this node's own entry
+        const bool reflect = (s == -1) || from_out || (from_in && wall);
+        const unsigned m = (unsigned)(local ? i : s);
+        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + m * ES;
+        const raw r0 = gload<raw>(fin, off);
+        const raw r1 = gload<raw>(fin, off + spec);
         if constexpr (C::shifted) {
-            const float wk = (float)L::w[kk];
+            const float wk = (float)L::w[k];  // w of the opposite link is the same
             float s0, s1;
             if constexpr (NS) {
-                s0 = wk * (reflect ? sh_own0 : a.xin[m]);
-                s1 = wk * (reflect ? sh_own1 : a.xin[N + m]);
+                s0 = wk * (local ? sh_own0 : gload<float>(a.xin, m * 4u));
+                s1 = wk * (local ? sh_own1 : gload<float>(a.xin, m * 4u + xsp));
             } else {
                 s0 = wk * cg0;
                 s1 = wk * cg1;
@@ -192,20 +243,19 @@ __device__ inline void pull_node(const StepArgs& a, int x, int y, int z, long lo
             f[0][k] = C::dec(r0, CT(0));
             f[1][k] = C::dec(r1, CT(0));
         }
-        if (from_out) {
+        if (L::ex[k] == -1) {
             const CT frac = (CT)(L::w[L::opp[k]] / W_OUT);
-            f[0][k] -= frac * (CT)a.Q0;
-            f[1][k] -= frac * (CT)a.Q1;
+            f[0][k] = from_out ? f[0][k] - frac * (CT)a.Q0 : f[0][k];
+            f[1][k] = from_out ? f[1][k] - frac * (CT)a.Q1 : f[1][k];
         }
     }
-    if (inlet && !a.inlet_wall) {
+    const bool anti = inlet && !wall;
 #pragma unroll
-        for (int k = 0; k < L::Q; ++k) {
-            if (L::ex[k] == 1) {
-                const CT ww = (CT)(L::w[k] + L::w[L::opp[k]]);
-                f[0][k] = ww * (CT)a.Xin0 - f[0][L::opp[k]];
-                f[1][k] = ww * (CT)a.Xin1 - f[1][L::opp[k]];
-            }
+    for (int k = 0; k < L::Q; ++k) {
+        if (L::ex[k] == 1) {
+            const CT ww = (CT)(L::w[k] + L::w[L::opp[k]]);
+            f[0][k] = anti ? ww * (CT)a.Xin0 - f[0][L::opp[k]] : f[0][k];
+            f[1][k] = anti ? ww * (CT)a.Xin1 - f[1][L::opp[k]] : f[1][k];
         }
     }
     double s0 = 0.0, s1 = 0.0;
@@ -216,6 +266,17 @@ __device__ inline void pull_node(const StepArgs& a, int x, int y, int z, long lo
     }
     X0 = s0;
     X1 = s1;
+}
+
+// Pull of node (x, y, z) (dense n, compact i) through the global index map; returns NB_* bits.
+template <class L, int P, bool NS>
+__device__ inline uint32_t pull_node(const StepArgs& a, int x, int y, int z, long long n, int i,
+                                     typename Codec<P>::CT (&f)[2][L::Q], double& X0, double& X1)
+{
+    int si[L::Q];
+    const uint32_t nb = global_sources<L>(a, x, y, z, n, i, si);
+    gather<L, P, NS>(a, i, si, x == 0, x == a.nx - 1, f, X0, X1);
+    return nb;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -241,34 +302,41 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     double n0 = 0.0, n1 = 0.0;
     if (a.ms_mode == 0) {
         // Eq. 34 with Gamma = I: J = -[B]^-1 grad X (Cramer's rule), then |J| per species
-        const double det = B00 * B11 - B01 * B10;
+        const double rdet = 1.0 / (B00 * B11 - B01 * B10);
         double q0 = 0.0, q1 = 0.0;
 #pragma unroll
         for (int dd = 0; dd < DIMS; ++dd) {
-            const double J0 = -(B11 * g0[dd] - B01 * g1[dd]) / det;
-            const double J1 = -(B00 * g1[dd] - B10 * g0[dd]) / det;
+            const double J0 = -(B11 * g0[dd] - B01 * g1[dd]) * rdet;
+            const double J1 = -(B00 * g1[dd] - B10 * g0[dd]) * rdet;
             q0 += J0 * J0;
             q1 += J1 * J1;
         }
         n0 = sqrt(q0);
         n1 = sqrt(q1);
     }
-    const double r21 = (a.ms_mode == 0) ? (n1 + a.eps1) / (n0 + a.eps0) : a.rst21;
-    const double r12 = (a.ms_mode == 0) ? (n0 + a.eps0) / (n1 + a.eps1) : a.rst12;
+    double r21 = a.rst21, r12 = a.rst12;
+    if (a.ms_mode == 0) {
+        // flux-norm ratios |N_2|/|N_1| and |N_1|/|N_2| through one reciprocal
+        const double u = n1 + a.eps1, v = n0 + a.eps0;
+        const double ruv = 1.0 / (u * v);
+        r21 = u * u * ruv;
+        r12 = v * v * ruv;
+    }
     // Eq. 24 with N_i = sigma_i |N_i|; the inert species (sigma = 0) contributes X_3 / D_i3
     const double inv0 = (X1 - X0 * a.sgn12 * r21) * a.iD12 + X2 * a.iD13;
     const double inv1 = (X0 - X1 * a.sgn12 * r12) * a.iD12 + X2 * a.iD23;
-    // Eq. 25 with c_s^2 = 1/3
-    double t0 = 3.0 / inv0 + 0.5;
-    double t1 = 3.0 / inv1 + 0.5;
+    // Eq. 25 with c_s^2 = 1/3: tau = 3 D + 1/2, so 1/tau = (1/D) / (3 + (1/D) / 2); the clamp
+    // tau in [tau_min, tau_max] is applied as 1/tau in [1/tau_max, 1/tau_min]
+    double w0 = inv0 / (3.0 + 0.5 * inv0);
+    double w1 = inv1 / (3.0 + 0.5 * inv1);
     bool h = false;
-    if (!(t0 >= a.tau_min)) { t0 = a.tau_min; h = true; }
-    else if (t0 > a.tau_max) { t0 = a.tau_max; h = true; }
-    if (!(t1 >= a.tau_min)) { t1 = a.tau_min; h = true; }
-    else if (t1 > a.tau_max) { t1 = a.tau_max; h = true; }
+    if (!(w0 <= a.om_hi)) { w0 = a.om_hi; h = true; }
+    else if (w0 < a.om_lo) { w0 = a.om_lo; h = true; }
+    if (!(w1 <= a.om_hi)) { w1 = a.om_hi; h = true; }
+    else if (w1 < a.om_lo) { w1 = a.om_lo; h = true; }
     hit = h;
-    om0 = 1.0 / t0;
-    om1 = 1.0 / t1;
+    om0 = w0;
+    om1 = w1;
 }
 
 // central difference, one-sided next to a missing or solid neighbour, zero between two
@@ -282,36 +350,40 @@ __device__ inline double grad1(bool up, bool dn, double xu, double xc, double xd
 
 // BGK collision toward w_a X_s (Eq. 28-29) and store of the post-collision populations.
 template <class L, int P, bool NS>
-__device__ inline void collide_store(const StepArgs& a, long long n,
+__device__ inline void collide_store(const StepArgs& a, int n,
                                      typename Codec<P>::CT (&f)[2][L::Q], double X0, double X1,
                                      double om0, double om1)
 {
     using C = Codec<P>;
     using CT = typename C::CT;
     using raw = typename C::raw;
-    raw* __restrict__ fout = static_cast<raw*>(a.fout);
-    const long long N = a.N;
+    constexpr unsigned ES = sizeof(raw);
+    void* fout = a.fout;
+    const unsigned plane = (unsigned)a.P * ES;
+    const unsigned spec = (unsigned)L::Q * plane;
+    const unsigned base = (unsigned)n * ES;
     const CT o0 = (CT)om0, o1 = (CT)om1;
     const CT x0 = (CT)X0, x1 = (CT)X1;
     float c0 = (float)a.c0, c1 = (float)a.c1;
     if constexpr (NS) {
         c0 = (float)X0;
         c1 = (float)X1;
-        a.xout[n] = c0;
-        a.xout[N + n] = c1;
+        gstore<float>(a.xout, (unsigned)n * 4u, c0);
+        gstore<float>(a.xout, (unsigned)n * 4u + (unsigned)a.NF * 4u, c1);
     }
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const CT wk = (CT)L::w[k];
         const CT v0 = f[0][k] + o0 * (wk * x0 - f[0][k]);
         const CT v1 = f[1][k] + o1 * (wk * x1 - f[1][k]);
+        const unsigned off = base + (unsigned)k * plane;
         if constexpr (C::shifted) {
             const float wf = (float)L::w[k];
-            fout[(long long)k * N + n] = C::enc(v0, wf * c0);
-            fout[(long long)(L::Q + k) * N + n] = C::enc(v1, wf * c1);
+            gstore<raw>(fout, off, C::enc(v0, wf * c0));
+            gstore<raw>(fout, off + spec, C::enc(v1, wf * c1));
         } else {
-            fout[(long long)k * N + n] = C::enc(v0, CT(0));
-            fout[(long long)(L::Q + k) * N + n] = C::enc(v1, CT(0));
+            gstore<raw>(fout, off, C::enc(v0, CT(0)));
+            gstore<raw>(fout, off + spec, C::enc(v1, CT(0)));
         }
     }
 }

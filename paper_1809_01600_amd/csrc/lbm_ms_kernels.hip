@@ -4,8 +4,10 @@
 // from the neighbours (bounce-back and the x-boundary rules applied on the way), forms the
 // moments, takes the mole-fraction gradients from an LDS tile that also holds a one-node halo
 // (recomputed from the halo nodes' own pulls), solves the Maxwell-Stefan system in FP64 for the
-// relaxation times, collides and stores to the other buffer.  Populations are structure of
-// arrays [species][link][node] with x fastest, so a wavefront's loads and stores are coalesced
+// relaxation times, collides and stores to the other buffer.  Populations of fluid nodes only
+// are stored, structure of arrays [species][link][fluid node] with the fluid nodes numbered in
+// raster order (x fastest); a dense int32 map gives each voxel's fluid index (-1 = solid), so
+// solid voxels cost no population traffic while a wavefront's loads and stores stay contiguous
 // along x.
 #include <hip/hip_runtime.h>
 
@@ -14,114 +16,185 @@
 
 namespace lbmms {
 
+// Source slots of a node from an LDS-staged copy of the index map.  The staged region covers the
+// tile plus a two-node ring, so every source of a tile or halo node lies inside it.  sI points at
+// NPL planes of RY x RX ints; the node sits at column cx, row cy of relative plane zr (plane slot
+// (zr + 2) % NPL).  Lanes without a fluid node get zero slots (a harmless dummy gather).
+template <class L, int RX, int RY, int NPL>
+__device__ inline uint32_t lds_sources(const int* sI, int zr, int cx, int cy, int x, int nx, int i,
+                                       int (&si)[L::Q])
+{
+    uint32_t nb = 0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const int ex = L::ex[k], ey = L::ey[k], ez = L::ez[k];
+        if (k == 0) { si[k] = i; continue; }
+        if ((ex == -1 && x == nx - 1) || (ex == 1 && x == 0)) { si[k] = BOUNDARY; continue; }
+        const int slot = (zr - ez + 2 + NPL) % NPL;
+        si[k] = sI[(slot * RY + (cy - ey)) * RX + (cx - ex)];
+        nb |= axis_bit<L>(k, si[k]);
+    }
+    if (i < 0) {
+#pragma unroll
+        for (int k = 0; k < L::Q; ++k) si[k] = 0;
+    }
+    return nb;
+}
+
+// Halo ring position of thread t (t < 2 TX + 2 TY): tile-relative column hx and row hy.
+template <int TX, int TY>
+__device__ inline void halo_pos(int t, int& hx, int& hy)
+{
+    if (t < TX) { hx = t; hy = -1; }
+    else if (t < 2 * TX) { hx = t - TX; hy = TY; }
+    else if (t < 2 * TX + TY) { hx = -1; hy = t - 2 * TX; }
+    else if (t < 2 * TX + 2 * TY) { hx = TX; hy = t - 2 * TX - TY; }
+    else { hx = 0; hy = 0; }
+}
+
+// Stage the index map of plane z (periodic) for the region x in [x0-2, x0+TX+2), y in
+// [y0-2, y0+TY+2) into dst; columns outside the box read -2.
+template <int RX, int RY>
+__device__ inline void stage_plane(const StepArgs& a, int x0, int y0, int z, int* dst)
+{
+    const long long zb = (long long)((z % a.nz + a.nz) % a.nz) * a.nx * a.ny;
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int rx = t % RX, ry = t / RX;
+        const int gx = x0 - 2 + rx;
+        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        dst[t] = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
-// 2D (D2Q9): one workgroup = 64 x TY output tile + one-node halo ring, all pulls in flight at once
+// 2D (D2Q9): a work list of 64 x TY tiles.  Each tile record names its instance (one problem of
+// a batch), its origin, and two entry lists built on the host: the tile's fluid nodes and the
+// fluid nodes outside them whose moments the tile's gradients read (the halo).  Entries are LDS
+// coordinates (cx, cy) of the (TX + 2) x (TY + 2) moment tile, packed as cy << 8 | cx.  Every
+// lane works on a fluid node; two memory round trips (staged index map, then all population
+// loads of the tile and its halo at once).  Workgroup = 32 TY lanes, so a lane holds at most
+// two of the tile's 64 TY nodes.
 // ---------------------------------------------------------------------------------------------
 template <int P, bool NS, int TY>
-__global__ __launch_bounds__(64 * TY) void k_step2d(StepArgs a)
+__global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__ insts,
+                                                    const int4* __restrict__ tiles,
+                                                    const unsigned* __restrict__ ent)
 {
     using L = D2Q9;
     using CT = typename Codec<P>::CT;
-    constexpr int TX = 64;
+    constexpr int TX = 64, RX = TX + 4, RY = TY + 4, BS = 32 * TY;
+    __shared__ int sI[RY * RX];
     __shared__ double sX[2][TY + 2][TX + 2];
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int x0 = (tile % a.tiles_x) * TX;
-    const int y0 = (tile / a.tiles_x) * TY;
-    const int lx = threadIdx.x & (TX - 1);
-    const int ly = threadIdx.x / TX;
-    const int x = x0 + lx;
-    const int yr = y0 + ly;
-    const int y = yr % a.ny;  // rows past the end hold the periodic image
-    const bool own = (x < a.nx) && (yr < a.ny);
-    const long long n = (long long)y * a.nx + x;
-    const uint32_t d = (x < a.nx) ? a.desc[n] : 0u;
+    const unsigned tb = (unsigned)tile * 32u;
+    const int4 t0 = make_int4(gload<int>(tiles, tb), gload<int>(tiles, tb + 4u),
+                              gload<int>(tiles, tb + 8u), 0);  // x0, y0, instance
+    const int4 t1 = make_int4(gload<int>(tiles, tb + 16u), gload<int>(tiles, tb + 20u),
+                              gload<int>(tiles, tb + 24u), gload<int>(tiles, tb + 28u));  // own/halo offsets, counts
+    const StepArgs& a = insts[t0.z];
+    const int x0 = t0.x, y0 = t0.y;
+    // entry lists first (they depend only on the tile record), then the staged index map
+    const bool two = t1.y > BS;  // workgroup-uniform: a second own node per lane
+    const unsigned dummy = (1u << 8) | 1u;
+    unsigned pe[3];
+    pe[0] = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
+    pe[1] = two && threadIdx.x + BS < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x + BS) * 4u) : dummy;
+    pe[2] = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
+    stage_plane<RX, RY>(a, x0, y0, 0, sI);
+    __syncthreads();
 
-    CT f[2][L::Q];
-    double X0 = 0.0, X1 = 0.0;
-    if (d & FLUID) pull_node<L, P, NS>(a, x, y, 0, n, d, f, X0, X1);
-    sX[0][ly + 1][lx + 1] = X0;
-    sX[1][ly + 1][lx + 1] = X1;
-
-    // halo ring: row below, row above, column left, column right
-    const int t = threadIdx.x;
-    if (t < 2 * TX + 2 * TY) {
-        int hx, hyr, sx, sy;
-        if (t < TX) { hx = x0 + t; hyr = y0 - 1; sx = t + 1; sy = 0; }
-        else if (t < 2 * TX) { hx = x0 + t - TX; hyr = y0 + TY; sx = t - TX + 1; sy = TY + 1; }
-        else if (t < 2 * TX + TY) { hx = x0 - 1; hyr = y0 + t - 2 * TX; sx = 0; sy = t - 2 * TX + 1; }
-        else { hx = x0 + TX; hyr = y0 + t - 2 * TX - TY; sx = TX + 1; sy = t - 2 * TX - TY + 1; }
-        const int hy = ((hyr % a.ny) + a.ny) % a.ny;
-        double h0 = 0.0, h1 = 0.0;
-        if (hx >= 0 && hx < a.nx) {
-            const long long hn = (long long)hy * a.nx + hx;
-            const uint32_t hd = a.desc[hn];
-            if (hd & FLUID) {
-                CT hf[2][L::Q];
-                pull_node<L, P, NS>(a, hx, hy, 0, hn, hd, hf, h0, h1);
-            }
+    // own nodes (entries t and t + BS) and the first halo entry: all loads issued together
+    CT f[2][2][L::Q];
+    double X0[2] = {0.0, 0.0}, X1[2] = {0.0, 0.0};
+    int io[2] = {-1, -1}, cxo[2], cyo[2];
+    uint32_t nbo[2] = {0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        cxo[u] = pe[u] & 255u;
+        cyo[u] = pe[u] >> 8;
+        if (u == 1 && !two) break;
+        const bool job = threadIdx.x + u * BS < (unsigned)t1.y;
+        io[u] = job ? sI[(cyo[u] + 1) * RX + cxo[u] + 1] : -1;
+        const int x = x0 + cxo[u] - 1;
+        int si[L::Q];
+        nbo[u] = lds_sources<L, RX, RY, 1>(sI, -2, cxo[u] + 1, cyo[u] + 1, x, a.nx, io[u], si);
+        gather<L, P, NS>(a, io[u] < 0 ? 0 : io[u], si, io[u] >= 0 && x == 0,
+                         io[u] >= 0 && x == a.nx - 1, f[u], X0[u], X1[u]);
+    }
+    if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
+        const int cx = pe[2] & 255u, cy = pe[2] >> 8;
+        const bool job = threadIdx.x < (unsigned)t1.w;
+        const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
+        const int x = x0 + cx - 1;
+        int si[L::Q];
+        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+        CT hf[2][L::Q];
+        double h0, h1;
+        gather<L, P, NS>(a, hi < 0 ? 0 : hi, si, hi >= 0 && x == 0, hi >= 0 && x == a.nx - 1, hf, h0, h1);
+        if (job) {
+            sX[0][cy][cx] = h0;
+            sX[1][cy][cx] = h1;
         }
-        sX[0][sy][sx] = h0;
-        sX[1][sy][sx] = h1;
+    }
+    // remaining halo entries (only where the tile wraps onto itself in y)
+    for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
+        const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
+        const int cx = pw & 255u, cy = pw >> 8;
+        const int hi = sI[(cy + 1) * RX + cx + 1];
+        const int x = x0 + cx - 1;
+        int si[L::Q];
+        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+        CT hf[2][L::Q];
+        double h0, h1;
+        gather<L, P, NS>(a, hi, si, x == 0, x == a.nx - 1, hf, h0, h1);
+        sX[0][cy][cx] = h0;
+        sX[1][cy][cx] = h1;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (io[u] >= 0) {
+            sX[0][cyo[u]][cxo[u]] = X0[u];
+            sX[1][cyo[u]][cxo[u]] = X1[u];
+        }
     }
     __syncthreads();
 
-    if (own && (d & FLUID)) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (io[u] < 0) continue;
+        const int cx = cxo[u], cy = cyo[u];
+        const uint32_t nb = nbo[u];
         double g0[3], g1[3];
-        const int cx = lx + 1, cy = ly + 1;
-        const bool xp = d & NB_XP, xm = d & NB_XM, yp = d & NB_YP, ym = d & NB_YM;
-        g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
-        g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
-        g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
-        g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
+        const bool xp = nb & NB_XP, xm = nb & NB_XM, yp = nb & NB_YP, ym = nb & NB_YM;
+        g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0[u], sX[0][cy][cx - 1]);
+        g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1[u], sX[1][cy][cx - 1]);
+        g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0[u], sX[0][cy - 1][cx]);
+        g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1[u], sX[1][cy - 1][cx]);
         g0[2] = g1[2] = 0.0;
         double om0, om1;
         bool hit;
-        ms_relax<2>(a, X0, X1, g0, g1, (d & OUTLET) != 0, om0, om1, hit);
-        if (hit) a.flags[0] = 1u;
-        collide_store<L, P, NS>(a, n, f, X0, X1, om0, om1);
+        ms_relax<2>(a, X0[u], X1[u], g0, g1, x0 + cx - 1 == a.nx - 1, om0, om1, hit);
+        if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+        collide_store<L, P, NS>(a, io[u], f[u], X0[u], X1[u], om0, om1);
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// 3D (D3Q19): one workgroup = 64 x TY column tile marching through CZ planes; x/y gradients
-// from a 3-slot LDS ring of planes (tile + halo ring), z gradients from the column's own
-// rolling registers.  One barrier per plane.
+// 3D (D3Q19): one workgroup = 64 x TY column tile marching through CZ planes.  The index map is
+// staged in a 5-plane LDS ring one plane ahead; x/y gradients come from a 3-slot LDS ring of
+// plane moments (tile + halo ring), z gradients from the column's own rolling registers.  One
+// barrier per plane.
 // ---------------------------------------------------------------------------------------------
-template <int P, bool NS, int TY>
-__device__ inline void plane_halo(const StepArgs& a, int x0, int y0, int z, double (*sX)[TY + 2][66])
-{
-    using L = D3Q19;
-    using CT = typename Codec<P>::CT;
-    constexpr int TX = 64;
-    const int t = threadIdx.x;
-    if (t < 2 * TX + 2 * TY) {
-        int hx, hyr, sx, sy;
-        if (t < TX) { hx = x0 + t; hyr = y0 - 1; sx = t + 1; sy = 0; }
-        else if (t < 2 * TX) { hx = x0 + t - TX; hyr = y0 + TY; sx = t - TX + 1; sy = TY + 1; }
-        else if (t < 2 * TX + TY) { hx = x0 - 1; hyr = y0 + t - 2 * TX; sx = 0; sy = t - 2 * TX + 1; }
-        else { hx = x0 + TX; hyr = y0 + t - 2 * TX - TY; sx = TX + 1; sy = t - 2 * TX - TY + 1; }
-        const int hy = ((hyr % a.ny) + a.ny) % a.ny;
-        double h0 = 0.0, h1 = 0.0;
-        if (hx >= 0 && hx < a.nx) {
-            const long long hn = ((long long)z * a.ny + hy) * a.nx + hx;
-            const uint32_t hd = a.desc[hn];
-            if (hd & FLUID) {
-                CT hf[2][L::Q];
-                pull_node<L, P, NS>(a, hx, hy, z, hn, hd, hf, h0, h1);
-            }
-        }
-        sX[0][sy][sx] = h0;
-        sX[1][sy][sx] = h1;
-    }
-}
-
 template <int P, bool NS, int TY, int CZ>
 __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
 {
     using L = D3Q19;
     using CT = typename Codec<P>::CT;
-    constexpr int TX = 64;
+    constexpr int TX = 64, RX = TX + 4, RY = TY + 4, NPL = 5;
+    constexpr int NHALO = 2 * TX + 2 * TY;
+    constexpr int HWAVES = (NHALO + 63) / 64;
+    __shared__ int sI[NPL * RY * RX];
     __shared__ double sX[3][2][TY + 2][TX + 2];
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -133,55 +206,93 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
     const int lx = threadIdx.x & (TX - 1);
     const int ly = threadIdx.x / TX;
     const int x = x0 + lx;
-    const int yr = y0 + ly;
-    const int y = yr % a.ny;
-    const bool own = (x < a.nx) && (yr < a.ny);
-    const long long plane = (long long)a.nx * a.ny;
-    const long long col = (long long)y * a.nx + x;
+    const bool own = (x < a.nx) && (y0 + ly < a.ny);
+    const bool in_x = x < a.nx;
+    int hx = 0, hy = 0;
+    halo_pos<TX, TY>(threadIdx.x, hx, hy);
+    const int hgx = x0 + hx;
+    const bool hjob = threadIdx.x < NHALO && hgx >= 0 && hgx < a.nx;
 
-    // plane z0 - 1 (periodic): moments only, for the z gradient of plane z0
-    double Xm0 = 0.0, Xm1 = 0.0;
+    // planes z0-2 .. z0+2 (relative -2 .. 2) into the ring
+    for (int zr = -2; zr <= 2; ++zr)
+        stage_plane<RX, RY>(a, x0, y0, z0 + zr, sI + ((zr + 2) % NPL) * RY * RX);
+    __syncthreads();
+
+    // plane z0-1: moments only (z gradient of plane z0); plane z0: populations and moments
+    double Xm0, Xm1, Xc0, Xc1;
+    CT fc[2][L::Q];
+    int ic;
+    uint32_t nbc;
     {
-        const int zm = (z0 == 0) ? a.nz - 1 : z0 - 1;
-        const long long nm = zm * plane + col;
-        const uint32_t dm = (x < a.nx) ? a.desc[nm] : 0u;
-        if (dm & FLUID) {
-            CT tf[2][L::Q];
-            pull_node<L, P, NS>(a, x, y, zm, nm, dm, tf, Xm0, Xm1);
+        const int im = sI[((1) * RY + ly + 2) * RX + lx + 2];
+        int si[L::Q];
+        lds_sources<L, RX, RY, NPL>(sI, -1, lx + 2, ly + 2, x, a.nx, in_x ? im : -1, si);
+        CT tf[2][L::Q];
+        gather<L, P, NS>(a, (in_x && im >= 0) ? im : 0, si, x == 0, x == a.nx - 1, tf, Xm0, Xm1);
+        if (!(in_x && im >= 0)) Xm0 = Xm1 = 0.0;
+        ic = in_x ? sI[((2) * RY + ly + 2) * RX + lx + 2] : -1;
+        nbc = lds_sources<L, RX, RY, NPL>(sI, 0, lx + 2, ly + 2, x, a.nx, ic, si);
+        gather<L, P, NS>(a, ic < 0 ? 0 : ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1);
+        if (ic < 0) Xc0 = Xc1 = 0.0;
+        double h0 = 0.0, h1 = 0.0;
+        if (threadIdx.x < HWAVES * 64) {
+            const int hi = hjob ? sI[((2) * RY + hy + 2) * RX + hx + 2] : -1;
+            int hsi[L::Q];
+            lds_sources<L, RX, RY, NPL>(sI, 0, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
+            CT hf[2][L::Q];
+            gather<L, P, NS>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+            if (hi < 0) h0 = h1 = 0.0;
+        }
+        sX[0][0][ly + 1][lx + 1] = Xc0;
+        sX[0][1][ly + 1][lx + 1] = Xc1;
+        if (threadIdx.x < NHALO) {
+            sX[0][0][hy + 1][hx + 1] = h0;
+            sX[0][1][hy + 1][hx + 1] = h1;
         }
     }
-    // plane z0: populations kept for the collision, moments into LDS slot 0
-    CT fc[2][L::Q];
-    double Xc0 = 0.0, Xc1 = 0.0;
-    uint32_t dc = (x < a.nx) ? a.desc[z0 * plane + col] : 0u;
-    if (dc & FLUID) pull_node<L, P, NS>(a, x, y, z0, z0 * plane + col, dc, fc, Xc0, Xc1);
-    sX[0][0][ly + 1][lx + 1] = Xc0;
-    sX[0][1][ly + 1][lx + 1] = Xc1;
-    plane_halo<P, NS, TY>(a, x0, y0, z0, sX[0]);
+    __syncthreads();  // the ring slot of plane z0-2 is free from here on
 
-    for (int i = 0; i < CZ; ++i) {
-        const int zi = z0 + i;
+    for (int it = 0; it < CZ; ++it) {
+        const int zi = z0 + it;
         if (zi >= a.nz) break;  // uniform across the workgroup
-        const int zp = (zi + 1 == a.nz) ? 0 : zi + 1;
-        const long long np = zp * plane + col;
-        const uint32_t dn = (x < a.nx) ? a.desc[np] : 0u;
+        // stage plane it+3 (read by the next iteration's pull)
+        stage_plane<RX, RY>(a, x0, y0, z0 + it + 3, sI + ((it + 5) % NPL) * RY * RX);
+        // pull plane it+1: own column (populations kept) and, if the next plane is output, its halo
+        const int zr = it + 1;
+        const int pslot = (zr + 2) % NPL;
+        const int in_ = in_x ? sI[(pslot * RY + ly + 2) * RX + lx + 2] : -1;
+        int si[L::Q];
+        const uint32_t nbn = lds_sources<L, RX, RY, NPL>(sI, zr, lx + 2, ly + 2, x, a.nx, in_, si);
         CT fn[2][L::Q];
-        double Xp0 = 0.0, Xp1 = 0.0;
-        if (dn & FLUID) pull_node<L, P, NS>(a, x, y, zp, np, dn, fn, Xp0, Xp1);
-        const bool need_next = (i + 1 < CZ) && (zi + 1 < a.nz);
+        double Xp0, Xp1;
+        gather<L, P, NS>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1);
+        if (in_ < 0) Xp0 = Xp1 = 0.0;
+        const bool need_next = (it + 1 < CZ) && (zi + 1 < a.nz);
+        const int s_next = (it + 1) % 3;
         if (need_next) {
-            const int s = (i + 1) % 3;
-            sX[s][0][ly + 1][lx + 1] = Xp0;
-            sX[s][1][ly + 1][lx + 1] = Xp1;
-            plane_halo<P, NS, TY>(a, x0, y0, zp, sX[s]);
+            double h0 = 0.0, h1 = 0.0;
+            if (threadIdx.x < HWAVES * 64) {
+                const int hi = hjob ? sI[(pslot * RY + hy + 2) * RX + hx + 2] : -1;
+                int hsi[L::Q];
+                lds_sources<L, RX, RY, NPL>(sI, zr, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
+                CT hf[2][L::Q];
+                gather<L, P, NS>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+                if (hi < 0) h0 = h1 = 0.0;
+            }
+            sX[s_next][0][ly + 1][lx + 1] = Xp0;
+            sX[s_next][1][ly + 1][lx + 1] = Xp1;
+            if (threadIdx.x < NHALO) {
+                sX[s_next][0][hy + 1][hx + 1] = h0;
+                sX[s_next][1][hy + 1][hx + 1] = h1;
+            }
         }
         __syncthreads();
-        if (own && (dc & FLUID)) {
-            const int s = i % 3;
+        if (own && ic >= 0) {
+            const int s = it % 3;
             const int cx = lx + 1, cy = ly + 1;
             double g0[3], g1[3];
-            const bool xp = dc & NB_XP, xm = dc & NB_XM, yp = dc & NB_YP, ym = dc & NB_YM;
-            const bool zpf = dc & NB_ZP, zmf = dc & NB_ZM;
+            const bool xp = nbc & NB_XP, xm = nbc & NB_XM, yp = nbc & NB_YP, ym = nbc & NB_YM;
+            const bool zpf = nbc & NB_ZP, zmf = nbc & NB_ZM;
             g0[0] = grad1(xp, xm, sX[s][0][cy][cx + 1], Xc0, sX[s][0][cy][cx - 1]);
             g1[0] = grad1(xp, xm, sX[s][1][cy][cx + 1], Xc1, sX[s][1][cy][cx - 1]);
             g0[1] = grad1(yp, ym, sX[s][0][cy + 1][cx], Xc0, sX[s][0][cy - 1][cx]);
@@ -190,13 +301,14 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
             g1[2] = grad1(zpf, zmf, Xp1, Xc1, Xm1);
             double om0, om1;
             bool hit;
-            ms_relax<3>(a, Xc0, Xc1, g0, g1, (dc & OUTLET) != 0, om0, om1, hit);
-            if (hit) a.flags[0] = 1u;
-            collide_store<L, P, NS>(a, (long long)zi * plane + col, fc, Xc0, Xc1, om0, om1);
+            ms_relax<3>(a, Xc0, Xc1, g0, g1, x == a.nx - 1, om0, om1, hit);
+            if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+            collide_store<L, P, NS>(a, ic, fc, Xc0, Xc1, om0, om1);
         }
         Xm0 = Xc0; Xm1 = Xc1;
         Xc0 = Xp0; Xc1 = Xp1;
-        dc = dn;
+        ic = in_;
+        nbc = nbn;
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
             fc[0][k] = fn[0][k];
@@ -218,26 +330,27 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
     const long long N = a.N;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
-        const bool fl = a.desc[n] & FLUID;
-        const double v0 = fl ? (X ? X[n] : u0) : 0.0;
-        const double v1 = fl ? (X ? X[N + n] : u1) : 0.0;
+        const int i = a.idx[n];
+        if (i < 0) continue;
+        const double v0 = X ? X[n] : u0;
+        const double v1 = X ? X[N + n] : u1;
         float c0 = (float)a.c0, c1 = (float)a.c1;
         if constexpr (NS) {
             c0 = (float)v0;
             c1 = (float)v1;
-            a.xout[n] = c0;
-            a.xout[N + n] = c1;
+            a.xout[i] = c0;
+            a.xout[a.NF + i] = c1;
         }
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
             const CT e0 = (CT)(L::w[k] * v0), e1 = (CT)(L::w[k] * v1);
             if constexpr (C::shifted) {
                 const float wf = (float)L::w[k];
-                fout[(long long)k * N + n] = fl ? C::enc(e0, wf * c0) : (raw)0.0f;
-                fout[(long long)(L::Q + k) * N + n] = fl ? C::enc(e1, wf * c1) : (raw)0.0f;
+                fout[(long long)k * a.P + i] = C::enc(e0, wf * c0);
+                fout[(long long)(L::Q + k) * a.P + i] = C::enc(e1, wf * c1);
             } else {
-                fout[(long long)k * N + n] = C::enc(e0, CT(0));
-                fout[(long long)(L::Q + k) * N + n] = C::enc(e1, CT(0));
+                fout[(long long)k * a.P + i] = C::enc(e0, CT(0));
+                fout[(long long)(L::Q + k) * a.P + i] = C::enc(e1, CT(0));
             }
         }
     }
@@ -245,27 +358,26 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
 
 // moments of the stored post-collision state (collision conserves them)
 template <class L, int P, bool NS>
-__device__ inline void node_moments(const StepArgs& a, long long n, double& X0, double& X1)
+__device__ inline void node_moments(const StepArgs& a, int i, double& X0, double& X1)
 {
     using C = Codec<P>;
     using raw = typename C::raw;
     const raw* fin = static_cast<const raw*>(a.fin);
-    const long long N = a.N;
     float c0 = (float)a.c0, c1 = (float)a.c1;
     if constexpr (NS) {
-        c0 = a.xin[n];
-        c1 = a.xin[N + n];
+        c0 = a.xin[i];
+        c1 = a.xin[a.NF + i];
     }
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         if constexpr (C::shifted) {
             const float wf = (float)L::w[k];
-            s0 += (double)C::dec(fin[(long long)k * N + n], wf * c0);
-            s1 += (double)C::dec(fin[(long long)(L::Q + k) * N + n], wf * c1);
+            s0 += (double)C::dec(fin[(long long)k * a.P + i], wf * c0);
+            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], wf * c1);
         } else {
-            s0 += (double)C::dec(fin[(long long)k * N + n], 0);
-            s1 += (double)C::dec(fin[(long long)(L::Q + k) * N + n], 0);
+            s0 += (double)C::dec(fin[(long long)k * a.P + i], 0);
+            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], 0);
         }
     }
     X0 = s0;
@@ -305,18 +417,17 @@ __global__ __launch_bounds__(256) void k_residual(StepArgs a, double* snap, int 
                                                   double* partial)
 {
     double v[6] = {0, 0, 0, 0, 0, 0};
-    const long long N = a.N;
-    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
-         n += (long long)gridDim.x * blockDim.x) {
-        if (!(a.desc[n] & FLUID)) continue;
+    const long long NF = a.NF;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < NF;
+         i += (long long)gridDim.x * blockDim.x) {
         double X0, X1;
-        node_moments<L, P, NS>(a, n, X0, X1);
+        node_moments<L, P, NS>(a, (int)i, X0, X1);
         const double X2 = 1.0 - X0 - X1;
         if (update) {
-            const double d0 = X0 - snap[n], d1 = X1 - snap[N + n];
+            const double d0 = X0 - snap[i], d1 = X1 - snap[NF + i];
             v[0] += d0 * d0 + d1 * d1;
-            snap[n] = X0;
-            snap[N + n] = X1;
+            snap[i] = X0;
+            snap[NF + i] = X1;
         }
         v[1] += X0 * X0 + X1 * X1;
         v[2] += X0;
@@ -351,22 +462,21 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
     const raw* fin = static_cast<const raw*>(a.fin);
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     const long long face = (long long)a.ny * a.nz;
-    const long long N = a.N;
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < face;
          k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k % a.ny), z = (int)(k / a.ny);
         for (int side = 0; side < 2; ++side) {
             const int x = side ? a.nx - 1 : 0;
             const long long n = ((long long)z * a.ny + y) * a.nx + x;
-            const uint32_t d = a.desc[n];
-            if (!(d & FLUID)) continue;
+            const int i = a.idx[n];
+            if (i < 0) continue;
             CT f[2][L::Q];
             double X0, X1;
-            pull_node<L, P, NS>(a, x, y, z, n, d, f, X0, X1);
+            pull_node<L, P, NS>(a, x, y, z, n, i, f, X0, X1);
             float c0 = (float)a.c0, c1 = (float)a.c1;
             if constexpr (NS) {
-                c0 = a.xin[n];
-                c1 = a.xin[N + n];
+                c0 = a.xin[i];
+                c1 = a.xin[a.NF + i];
             }
             double cross0 = 0.0, cross1 = 0.0;  // net +x transfer across the face
 #pragma unroll
@@ -376,11 +486,11 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                 double o0, o1;
                 if constexpr (C::shifted) {
                     const float wf = (float)L::w[q];
-                    o0 = C::dec(fin[(long long)q * N + n], wf * c0);
-                    o1 = C::dec(fin[(long long)(L::Q + q) * N + n], wf * c1);
+                    o0 = C::dec(fin[(long long)q * a.P + i], wf * c0);
+                    o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], wf * c1);
                 } else {
-                    o0 = C::dec(fin[(long long)q * N + n], 0);
-                    o1 = C::dec(fin[(long long)(L::Q + q) * N + n], 0);
+                    o0 = C::dec(fin[(long long)q * a.P + i], 0);
+                    o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], 0);
                 }
                 if (side == 0) {
                     if (L::ex[q] == 1) { cross0 += (double)f[0][q]; cross1 += (double)f[1][q]; }
@@ -395,7 +505,7 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                 v[4] += cross1;
             } else {
                 double m0, m1;
-                node_moments<L, P, NS>(a, n, m0, m1);
+                node_moments<L, P, NS>(a, i, m0, m1);
                 v[0] += m0;
                 v[1] += m1;
                 v[2] += 1.0;
@@ -415,8 +525,9 @@ __global__ void k_fields(StepArgs a, double* X)
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
         double X0 = 0.0, X1 = 0.0, X2 = 0.0;
-        if (a.desc[n] & FLUID) {
-            node_moments<L, P, NS>(a, n, X0, X1);
+        const int i = a.idx[n];
+        if (i >= 0) {
+            node_moments<L, P, NS>(a, i, X0, X1);
             X2 = 1.0 - X0 - X1;
         }
         X[n] = X0;
@@ -436,10 +547,11 @@ __global__ void k_populations(StepArgs a, int s, int q, double* out)
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (a.desc[n] & FLUID) {
+        const int i = a.idx[n];
+        if (i >= 0) {
             float c = (float)(s ? a.c1 : a.c0);
-            if constexpr (NS) c = a.xin[(long long)s * N + n];
-            const raw r = fin[((long long)s * L::Q + q) * N + n];
+            if constexpr (NS) c = a.xin[(long long)s * a.NF + i];
+            const raw r = fin[((long long)s * L::Q + q) * a.P + i];
             if constexpr (C::shifted) v = C::dec(r, (float)L::w[q] * c);
             else v = C::dec(r, 0);
         }
@@ -537,21 +649,41 @@ template <int P, bool NS>
 static hipError_t launch_step_p(hipStream_t st, const StepArgs& a, int lattice, int ty, int cz,
                                 int nblocks)
 {
-    if (lattice == 0) {
-        switch (ty) {
-        case 4: hipLaunchKernelGGL((k_step2d<P, NS, 4>), dim3(nblocks), dim3(64 * 4), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((k_step2d<P, NS, 8>), dim3(nblocks), dim3(64 * 8), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_step2d<P, NS, 16>), dim3(nblocks), dim3(64 * 16), 0, st, a); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        if (ty == 4 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 4, 16>), dim3(nblocks), dim3(256), 0, st, a);
-        else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
-        else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
-        else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
-        else return hipErrorInvalidValue;
+    if (lattice != 1) return hipErrorInvalidValue;
+    if (ty == 4 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 4, 16>), dim3(nblocks), dim3(256), 0, st, a);
+    else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
+    else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
+    else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int P, bool NS>
+static hipError_t launch_step2d_p(hipStream_t st, const StepArgs* insts, const int4* tiles,
+                                  const unsigned* ent, int ntiles, int ty)
+{
+    if (ntiles <= 0) return hipSuccess;
+    switch (ty) {
+    case 4: hipLaunchKernelGGL((k_step2d<P, NS, 4>), dim3(ntiles), dim3(32 * 4), 0, st, insts, tiles, ent); break;
+    case 8: hipLaunchKernelGGL((k_step2d<P, NS, 8>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent); break;
+    case 16: hipLaunchKernelGGL((k_step2d<P, NS, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,
+                         const unsigned* ent, int ntiles, int prec, int node_shift, int ty)
+{
+    switch (prec) {
+    case P_F64: return launch_step2d_p<P_F64, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F32: return launch_step2d_p<P_F32, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F16: return node_shift ? launch_step2d_p<P_F16, true>(st, insts, tiles, ent, ntiles, ty)
+                                  : launch_step2d_p<P_F16, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_BF16: return node_shift ? launch_step2d_p<P_BF16, true>(st, insts, tiles, ent, ntiles, ty)
+                                   : launch_step2d_p<P_BF16, false>(st, insts, tiles, ent, ntiles, ty);
+    }
+    return hipErrorInvalidValue;
 }
 
 int tile_options(int lattice, int* ty, int* cz, int cap)

@@ -1,5 +1,5 @@
 // Host runtime behind the C ABI of include/lbm_ms.h: handle state, workspace layout, the pore-space
-// clean-up and node descriptors, the physical-to-lattice conversion, the stepping loop and the
+// clean-up and the fluid index map, the physical-to-lattice conversion, the stepping loop and the
 // reductions.  Every per-node computation of the method runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,7 +26,8 @@ constexpr int RED_BLOCKS = 1024;    // per-block partials of the reductions
 constexpr uint64_t STATE_MAGIC = 0x314d534c42304c31ull;
 
 struct Layout {
-    size_t f[2], xn[2], desc, snap, field, part, prof, flags, scal, total;
+    size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
+    size_t tile_cap, ent_cap;
 };
 
 int q_of(int lattice) { return lattice == LBM_MS_D2Q9 ? 9 : 19; }
@@ -71,6 +73,14 @@ bool valid_params(const lbm_ms_params* p, std::string* why)
     return true;
 }
 
+// Elements between consecutive (species, link) population planes for n stored nodes: n rounded up
+// to 64 elements plus an odd multiple of 64, so the 2Q planes of one node do not sit a power of
+// two apart.
+long long plane_pitch(long long n)
+{
+    return ((n + 63) / 64) * 64 + 192;
+}
+
 Layout layout(const lbm_ms_params& p)
 {
     Layout L{};
@@ -78,22 +88,36 @@ Layout layout(const lbm_ms_params& p)
     const int q = q_of(p.lattice);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    const size_t fb = 2ull * q * N * elem_bytes(p.precision);
+    // sized for the all-fluid box; the fluid count is known only at set_geometry
+    const size_t fb = 2ull * q * (size_t)plane_pitch((long long)N) * elem_bytes(p.precision);
     L.f[0] = take(fb);
     L.f[1] = take(fb);
     const size_t xb = node_shift(p) ? 2ull * N * sizeof(float) : 0;
     L.xn[0] = take(xb);
     L.xn[1] = take(xb);
-    L.desc = take(N * sizeof(uint32_t));
+    L.idx = take(N * sizeof(int32_t));
     L.snap = take(2ull * N * sizeof(double));
     L.field = take(3ull * N * sizeof(double));
     L.part = take((size_t)RED_BLOCKS * 8 * sizeof(double));
     L.prof = take(2ull * p.nx * sizeof(double));
     L.flags = take(64);
     L.scal = take(64 * sizeof(double));
+    // 2D work lists: tiles of 64 x TY (TY >= 4) and their entries
+    L.tile_cap = 0;
+    L.ent_cap = 0;
+    if (p.lattice == LBM_MS_D2Q9) {
+        L.tile_cap = (size_t)((p.nx + 63) / 64) * (size_t)((p.ny + 3) / 4);
+        L.ent_cap = 3 * N + 4096;
+    }
+    L.inst = take(2 * sizeof(StepArgs));
+    L.tiles = take(L.tile_cap * 2 * sizeof(int4));
+    L.ent = take(L.ent_cap * sizeof(uint32_t));
     L.total = off;
     return L;
 }
+
+void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, int instance,
+                    uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent);
 
 }  // namespace
 
@@ -104,6 +128,7 @@ struct lbm_ms_s {
     char* ws = nullptr;
     int q = 9;
     long long N = 0;
+    long long P = 0;
     int cur = 0;
     // host state
     std::vector<uint8_t> mask;
@@ -113,6 +138,7 @@ struct lbm_ms_s {
     bool geom = false, bc = false, ready = false;
     long long steps = 0, snap_step = 0;
     int ty = 0, cz = 0;
+    int ntiles = 0;
     double* pinned = nullptr;
     std::string err;
 
@@ -142,9 +168,11 @@ struct lbm_ms_s {
         a.fout = ws + L.f[1 - in_buf];
         a.xin = node_shift(p) ? reinterpret_cast<const float*>(ws + L.xn[in_buf]) : nullptr;
         a.xout = node_shift(p) ? reinterpret_cast<float*>(ws + L.xn[1 - in_buf]) : nullptr;
-        a.desc = reinterpret_cast<const uint32_t*>(ws + L.desc);
+        a.idx = reinterpret_cast<const int*>(ws + L.idx);
         a.flags = reinterpret_cast<unsigned*>(ws + L.flags);
         a.N = N;
+        a.NF = n_fluid;
+        a.P = P;
         a.nx = p.nx;
         a.ny = p.ny;
         a.nz = p.nz;
@@ -166,8 +194,8 @@ struct lbm_ms_s {
         a.rst12 = std::fabs((double)p.nu[0]) / std::fabs((double)p.nu[1]);
         a.c0 = Xin[0];
         a.c1 = Xin[1];
-        a.tau_min = tau_min;
-        a.tau_max = tau_max;
+        a.om_lo = 1.0 / tau_max;
+        a.om_hi = 1.0 / tau_min;
         a.ms_mode = p.ms_mode;
         a.inlet_wall = p.inlet_mode == LBM_MS_INLET_WALL ? 1 : 0;
         return a;
@@ -179,10 +207,41 @@ struct lbm_ms_s {
         return (int)(tx * tyy * tz);
     }
     int sync() { return hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+    // instance table of both step parities (read by the 2D work-list kernel)
+    int upload_tables()
+    {
+        StepArgs t[2] = {args(0), args(1)};
+        int rc = sync();
+        if (rc) return rc;
+        std::memcpy(pinned + 64, t, sizeof(t));
+        rc = hip(hipMemcpyAsync(ws + L.inst, pinned + 64, sizeof(t), hipMemcpyHostToDevice, stream),
+                 "instance table upload");
+        if (rc) return rc;
+        return sync();
+    }
+
+    int upload_tiles()
+    {
+        if (p.lattice != LBM_MS_D2Q9 || !geom) return LBM_MS_OK;
+        std::vector<int4> tl;
+        std::vector<uint32_t> en;
+        build_tiles_2d(p.nx, p.ny, ty, mask, 0, 0, tl, en);
+        if (tl.size() / 2 > L.tile_cap || en.size() > L.ent_cap)
+            return fail(LBM_MS_E_NOMEM, "work list exceeds its workspace share");
+        int rc = hip(hipMemcpyAsync(ws + L.tiles, tl.data(), tl.size() * sizeof(int4),
+                                    hipMemcpyHostToDevice, stream), "tile upload");
+        if (rc) return rc;
+        rc = hip(hipMemcpyAsync(ws + L.ent, en.data(), en.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, stream), "entry upload");
+        if (rc) return rc;
+        ntiles = (int)(tl.size() / 2);
+        return sync();
+    }
 };
 
 // ---------------------------------------------------------------------------------------------
-// pore-space clean-up and node descriptors (host)
+// pore-space clean-up and the fluid index map (host)
 // ---------------------------------------------------------------------------------------------
 namespace {
 
@@ -246,42 +305,61 @@ long long clean_pores(const lbm_ms_params& p, std::vector<uint8_t>& solid)
     return open;
 }
 
-void build_descriptors(const lbm_ms_params& p, const std::vector<uint8_t>& solid,
-                       std::vector<uint32_t>& desc)
+// Fluid nodes are numbered in raster order (x fastest); solid voxels map to -1.
+long long build_index(const std::vector<uint8_t>& solid, std::vector<int32_t>& idx)
 {
-    const HostLattice H = host_lattice(p.lattice);
-    const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const long long N = (long long)nx * ny * nz;
-    desc.assign(N, 0u);
-    auto fluid_at = [&](int x, int y, int z) -> bool {
-        if (x < 0 || x >= nx) return false;
-        y = (y % ny + ny) % ny;
-        z = (z % nz + nz) % nz;
-        return !solid[((long long)z * ny + y) * nx + x];
-    };
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
-                const long long n = ((long long)z * ny + y) * nx + x;
-                if (solid[n]) continue;
-                uint32_t d = FLUID;
-                if (x == 0) d |= INLET;
-                if (x == nx - 1) d |= OUTLET;
-                for (int k = 1; k < H.q; ++k) {
-                    const int sx = x - H.e[k][0];
-                    if (sx < 0 || sx >= nx) continue;  // boundary links: handled by INLET/OUTLET
-                    if (!fluid_at(sx, y - H.e[k][1], z - H.e[k][2])) d |= 1u << k;
+    idx.assign(solid.size(), -1);
+    long long k = 0;
+    for (size_t n = 0; n < solid.size(); ++n)
+        if (!solid[n]) idx[n] = (int32_t)k++;
+    return k;
+}
+
+// 2D work list for 64 x TY tiles: per tile the fluid nodes it updates (own) and the other fluid
+// nodes whose moments its gradients read (halo: axis neighbours of own nodes, including rows
+// past the end of the box, which hold the periodic image).  Entries are moment-tile coordinates
+// (cx, cy) = (x - x0 + 1, y - y0 + 1) packed as cy << 8 | cx.  Tiles without fluid are dropped.
+void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, int instance,
+                    uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent)
+{
+    const int TX = 64;
+    auto fluid = [&](int x, int y) { return !solid[(size_t)y * nx + x]; };
+    std::vector<uint8_t> mark((TX + 2) * (ty + 2));
+    for (int y0 = 0; y0 < ny; y0 += ty)
+        for (int x0 = 0; x0 < nx; x0 += TX) {
+            const uint32_t own_off = ent_base + (uint32_t)ent.size();
+            std::fill(mark.begin(), mark.end(), 0);
+            auto is_own = [&](int cx, int cy) {
+                const int x = x0 + cx - 1, yr = y0 + cy - 1;
+                return cx >= 1 && cx <= TX && cy >= 1 && cy <= ty && x < nx && yr < ny && fluid(x, yr);
+            };
+            for (int cy = 1; cy <= ty; ++cy)
+                for (int cx = 1; cx <= TX; ++cx)
+                    if (is_own(cx, cy)) {
+                        ent.push_back((uint32_t)(cy << 8 | cx));
+                        mark[cy * (TX + 2) + cx] = 1;
+                    }
+            const uint32_t own_cnt = ent_base + (uint32_t)ent.size() - own_off;
+            if (own_cnt == 0) continue;
+            const uint32_t halo_off = ent_base + (uint32_t)ent.size();
+            static const int dxy[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+            for (int cy = 1; cy <= ty; ++cy)
+                for (int cx = 1; cx <= TX; ++cx) {
+                    if (!is_own(cx, cy)) continue;
+                    for (auto& d : dxy) {
+                        const int hx = cx + d[0], hy = cy + d[1];
+                        const int gx = x0 + hx - 1;
+                        if (gx < 0 || gx >= nx) continue;
+                        const int gy = ((y0 + hy - 1) % ny + ny) % ny;
+                        if (!fluid(gx, gy) || mark[hy * (TX + 2) + hx]) continue;
+                        mark[hy * (TX + 2) + hx] = 2;
+                        ent.push_back((uint32_t)(hy << 8 | hx));
+                    }
                 }
-                if (fluid_at(x - 1, y, z)) d |= NB_XM;
-                if (fluid_at(x + 1, y, z)) d |= NB_XP;
-                if (fluid_at(x, y - 1, z)) d |= NB_YM;
-                if (fluid_at(x, y + 1, z)) d |= NB_YP;
-                if (p.lattice == LBM_MS_D3Q19) {
-                    if (fluid_at(x, y, z - 1)) d |= NB_ZM;
-                    if (fluid_at(x, y, z + 1)) d |= NB_ZP;
-                }
-                desc[n] = d;
-            }
+            const uint32_t halo_cnt = ent_base + (uint32_t)ent.size() - halo_off;
+            tiles.push_back(make_int4(x0, y0, instance, 0));
+            tiles.push_back(make_int4((int)own_off, (int)own_cnt, (int)halo_off, (int)halo_cnt));
+        }
 }
 
 int default_tile_y(const lbm_ms_params& p)
@@ -307,7 +385,7 @@ bool tile_ok(int lattice, int ty, int cz)
     return false;
 }
 
-uint64_t param_hash(const lbm_ms_params& p)
+uint64_t param_hash(const lbm_ms_params& p, long long n_fluid)
 {
     // FNV-1a over the fields that fix the state layout
     uint64_t h = 1469598103934665603ull;
@@ -317,6 +395,7 @@ uint64_t param_hash(const lbm_ms_params& p)
     };
     mix(&p.lattice, sizeof(int)); mix(&p.nx, sizeof(int)); mix(&p.ny, sizeof(int));
     mix(&p.nz, sizeof(int)); mix(&p.precision, sizeof(int)); mix(&p.shift_mode, sizeof(int));
+    mix(&n_fluid, sizeof(n_fluid));
     return h;
 }
 
@@ -429,7 +508,9 @@ int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z)
         return h->fail(LBM_MS_E_ARG, "launch shape (%d, %d) not compiled", tile_y, chunk_z);
     h->ty = tile_y;
     h->cz = chunk_z;
-    return LBM_MS_OK;
+    int rc = h->upload_tiles();
+    if (rc) return rc;
+    return h->upload_tables();
 }
 
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
@@ -447,18 +528,19 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
         h->n_open = 0;
         for (long long n = h->p.nx - 1; n < h->N; n += h->p.nx) h->n_open += h->mask[n] ? 0 : 1;
     }
-    h->n_fluid = 0;
-    for (auto v : h->mask) h->n_fluid += v ? 0 : 1;
-    std::vector<uint32_t> desc;
-    build_descriptors(h->p, h->mask, desc);
-    int rc = h->hip(hipMemcpyAsync(h->at(h->L.desc), desc.data(), desc.size() * sizeof(uint32_t),
-                                   hipMemcpyHostToDevice, h->stream), "descriptor upload");
+    std::vector<int32_t> idx;
+    h->n_fluid = build_index(h->mask, idx);
+    h->P = plane_pitch(h->n_fluid);
+    int rc = h->hip(hipMemcpyAsync(h->at(h->L.idx), idx.data(), idx.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, h->stream), "index upload");
     if (rc) return rc;
     rc = h->sync();
     if (rc) return rc;
     h->geom = true;
     h->ready = false;
-    return LBM_MS_OK;
+    rc = h->upload_tiles();
+    if (rc) return rc;
+    return h->upload_tables();
 }
 
 int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host)
@@ -491,7 +573,7 @@ int lbm_ms_set_bc(lbm_ms_t h, const double X_in[3], double j)
     h->eps = h->p.eps_flux >= 0 ? h->p.eps_flux
                                 : 1e-2 * std::max(std::fabs(h->Q[0]), std::fabs(h->Q[1])) + 1e-14;
     h->bc = true;
-    return LBM_MS_OK;
+    return h->upload_tables();
 }
 
 static int init_common(lbm_ms_t h, const double* Xdev)
@@ -552,9 +634,17 @@ int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
     if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
     if (nsteps < 0) return h->fail(LBM_MS_E_ARG, "nsteps < 0");
     const int nb = h->nblocks_step();
+    const StepArgs* tab = reinterpret_cast<const StepArgs*>(h->ws + h->L.inst);
+    const int4* tiles = reinterpret_cast<const int4*>(h->ws + h->L.tiles);
+    const unsigned* ent = reinterpret_cast<const unsigned*>(h->ws + h->L.ent);
     for (int64_t t = 0; t < nsteps; ++t) {
-        StepArgs a = h->args(h->cur);
-        hipError_t e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb);
+        hipError_t e;
+        if (h->p.lattice == LBM_MS_D2Q9) {
+            e = launch_step2d(h->stream, tab + h->cur, tiles, ent, h->ntiles, h->prec(), h->ns(), h->ty);
+        } else {
+            StepArgs a = h->args(h->cur);
+            e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb);
+        }
         if (e != hipSuccess) return h->hip(e, "step kernel");
         h->cur ^= 1;
         ++h->steps;
@@ -757,14 +847,14 @@ struct StateHeader {
 int lbm_ms_save_state(lbm_ms_t h, void* buf, size_t* bytes)
 {
     if (!h || !bytes) return LBM_MS_E_ARG;
-    const size_t fb = 2ull * h->q * h->N * elem_bytes(h->p.precision);
-    const size_t xb = node_shift(h->p) ? 2ull * h->N * sizeof(float) : 0;
-    const size_t sb = 2ull * h->N * sizeof(double);
+    const size_t fb = 2ull * h->q * h->P * elem_bytes(h->p.precision);
+    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(float) : 0;
+    const size_t sb = 2ull * h->n_fluid * sizeof(double);
     const size_t need = sizeof(StateHeader) + fb + xb + sb;
     if (!buf) { *bytes = need; return LBM_MS_OK; }
     if (*bytes < need) return h->fail(LBM_MS_E_ARG, "buffer too small (%zu < %zu)", *bytes, need);
     if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
-    StateHeader H{STATE_MAGIC, param_hash(h->p), h->steps, h->snap_step, fb, xb, sb};
+    StateHeader H{STATE_MAGIC, param_hash(h->p, h->n_fluid), h->steps, h->snap_step, fb, xb, sb};
     char* c = (char*)buf;
     std::memcpy(c, &H, sizeof(H));
     c += sizeof(H);
@@ -789,10 +879,10 @@ int lbm_ms_load_state(lbm_ms_t h, const void* buf, size_t bytes)
     StateHeader H;
     if (bytes < sizeof(H)) return h->fail(LBM_MS_E_ARG, "blob too small");
     std::memcpy(&H, buf, sizeof(H));
-    const size_t fb = 2ull * h->q * h->N * elem_bytes(h->p.precision);
-    const size_t xb = node_shift(h->p) ? 2ull * h->N * sizeof(float) : 0;
-    const size_t sb = 2ull * h->N * sizeof(double);
-    if (H.magic != STATE_MAGIC || H.hash != param_hash(h->p) || H.fbytes != fb || H.xbytes != xb ||
+    const size_t fb = 2ull * h->q * h->P * elem_bytes(h->p.precision);
+    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(float) : 0;
+    const size_t sb = 2ull * h->n_fluid * sizeof(double);
+    if (H.magic != STATE_MAGIC || H.hash != param_hash(h->p, h->n_fluid) || H.fbytes != fb || H.xbytes != xb ||
         H.sbytes != sb || bytes < sizeof(H) + fb + xb + sb)
         return h->fail(LBM_MS_E_ARG, "checkpoint does not match this handle");
     const char* c = (const char*)buf + sizeof(H);

