@@ -192,6 +192,68 @@ int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, i
 /* Change the launch shape of an existing handle (one of lbm_ms_tile_options). */
 int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched solves (D2Q9): many independent porous slices of uneven size, each with its own
+ * geometry, inlet composition and current density, advanced together.  Every step is one kernel
+ * launch over the combined tile work list of all still-active instances; a converge call captures
+ * check_every steps into a hipGraph on the batch's own stream and replays it, checks every
+ * instance's residual, and retires converged instances from the work list.  One point of a
+ * polarization curve (Eq. 43 at each current density) per instance.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct lbm_ms_batch_s* lbm_ms_batch_t;
+
+typedef struct {
+    int nx, ny;                /* nodes of this instance (nz = 1) */
+    const uint8_t* solid;      /* host mask nx*ny, 1 = solid (cleaned as in lbm_ms_set_geometry) */
+    double X_in[3];            /* inlet mole fractions (Eq. 36) */
+    double j_A_per_m2;         /* current density (Eq. 39) */
+} lbm_ms_instance_desc;
+
+/* Device bytes for count instances with the shared parameters common (its lattice must be
+ * LBM_MS_D2Q9; nx, ny, nz are taken from each descriptor).  0 if invalid. */
+size_t lbm_ms_batch_workspace_bytes(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
+                                    int count);
+
+/* Create the batch: geometry clean-up, index maps, work lists and boundary data of every
+ * instance.  E_GEOM names the first instance whose outlet is unreachable (lbm_ms_batch_last_error).
+ * The caller owns d_workspace; the batch owns a stream of its own, ordered after common.stream
+ * at every call and before it on return. */
+int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
+                        void* d_workspace, size_t bytes, lbm_ms_batch_t* out);
+
+/* Initial state of every instance: uniform inlet composition (X0 == NULL) or a concatenation of
+ * per-instance [3][nx*ny] float64 fields, host (on_device = 0) or device memory.  Re-activates
+ * every instance. */
+int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device);
+
+/* nsteps steps of every active instance (one launch per step; asynchronous). */
+int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps);
+
+/* Steps in hipGraph-captured chunks of check_every until every instance's residual (as
+ * lbm_ms_residual) is below tol or max_steps is reached.  steps_taken[k], residual[k] per
+ * instance (may be NULL).  Returns E_NOT_CONVERGED if any instance did not converge. */
+int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int check_every,
+                          int64_t* steps_taken, double* residual);
+
+/* Per-instance overpotential (Eq. 43) into eta[count]. */
+int lbm_ms_batch_overpotential(lbm_ms_batch_t b, double* eta);
+
+/* The single-instance handle of instance k (for lbm_ms_get_fields, lbm_ms_residual, ...).  It
+ * stays owned by the batch; do not destroy it or step it on its own while the batch runs. */
+lbm_ms_t lbm_ms_batch_instance(lbm_ms_batch_t b, int k);
+
+/* Active instances, total fluid nodes of the active instances, and active tiles. */
+int lbm_ms_batch_stats(lbm_ms_batch_t b, int* active, int64_t* fluid_nodes, int* tiles);
+
+/* Launch shape of every instance (one of lbm_ms_tile_options for D2Q9). */
+int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y);
+
+/* Use (1) or bypass (0) hipGraph capture in lbm_ms_batch_converge (default 1). */
+int lbm_ms_batch_use_graphs(lbm_ms_batch_t b, int enable);
+
+const char* lbm_ms_batch_last_error(lbm_ms_batch_t b);
+void lbm_ms_batch_destroy(lbm_ms_batch_t b);
+
 const char* lbm_ms_last_error(lbm_ms_t h);
 const char* lbm_ms_status_string(int status);
 

@@ -1,0 +1,108 @@
+"""Launch-shape autotuner: times every compiled tile shape on the problem at hand and keeps the
+fastest, cached per (lattice, precision, shift, box size) in a JSON file.
+
+    from paper_1809_01600_amd import autotune
+    best = autotune.tune(solver)          # lbm_ms.Solver
+    best = autotune.tune_batch(batch)     # lbm_ms.Batch
+
+The cache lives at $LBM_MS_TUNE_CACHE (default ~/.cache/lbm_ms_tune.json).  Tuning changes only
+the launch shape; results are bitwise identical across shapes for a given storage precision.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import lbm_ms
+
+
+def cache_path() -> str:
+    return os.environ.get("LBM_MS_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "lbm_ms_tune.json"))
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except Exception:
+        return {}
+
+
+def _store(data):
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def _key(kind, lattice, precision, shift, dims):
+    return "%s|%s|p%d|s%d|%s" % (kind, lattice, precision, shift, "x".join(str(d) for d in dims))
+
+
+def tune(solver, steps: int = 100, warmup: int = 10, use_cache: bool = True):
+    """Pick the fastest tile shape for a single-problem solver (state is restored after)."""
+    p = solver.params
+    lat = "D2Q9" if p.lattice == lbm_ms.D2Q9 else "D3Q19"
+    key = _key("single", lat, p.precision, p.shift_mode, (p.nx, p.ny, p.nz))
+    data = _load() if use_cache else {}
+    if key in data:
+        ty, cz = data[key]["tile"]
+        solver.set_tile(ty, cz)
+        return tuple(data[key]["tile"])
+    blob = solver.save_state()
+    timings = {}
+    for ty, cz in lbm_ms.tile_options(p.lattice, p.precision):
+        solver.set_tile(ty, cz)
+        solver.step(warmup)
+        timings[(ty, cz)] = solver.time_steps(steps) / steps
+    best = min(timings, key=timings.get)
+    solver.set_tile(*best)
+    solver.load_state(blob)
+    data = _load()
+    data[key] = {"tile": list(best), "us_per_step": {"%d,%d" % k: v * 1e3 for k, v in timings.items()},
+                 "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if use_cache:
+        _store(data)
+    return best
+
+
+def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
+    """Pick the fastest tile height for a batch.  Tuning (re)initializes the batch to the uniform
+    inlet composition and advances it; initialize again before a solve."""
+    import torch
+    p = batch.params
+    sizes = sorted((c.nx, c.ny) for c in batch.cases)
+    key = _key("batch", "D2Q9", p.precision, p.shift_mode,
+               (len(sizes), sum(a * b for a, b in sizes)))
+    data = _load() if use_cache else {}
+    if key in data:
+        batch.set_tile(data[key]["tile"][0])
+        return tuple(data[key]["tile"])
+    timings = {}
+    batch.init()
+    for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9, p.precision):
+        batch.set_tile(ty)
+        batch.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch.step(steps)
+        e1.record()
+        e1.synchronize()
+        timings[ty] = e0.elapsed_time(e1) / steps
+    best = min(timings, key=timings.get)
+    batch.set_tile(best)
+    data = _load()
+    data[key] = {"tile": [best, 0], "ms_per_step": {str(k): v for k, v in timings.items()},
+                 "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if use_cache:
+        _store(data)
+    return (best, 0)

@@ -118,6 +118,7 @@ Layout layout(const lbm_ms_params& p)
 
 void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, int instance,
                     uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent);
+bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>& ent, int ty);
 
 }  // namespace
 
@@ -229,6 +230,7 @@ struct lbm_ms_s {
         build_tiles_2d(p.nx, p.ny, ty, mask, 0, 0, tl, en);
         if (tl.size() / 2 > L.tile_cap || en.size() > L.ent_cap)
             return fail(LBM_MS_E_NOMEM, "work list exceeds its workspace share");
+        if (!tiles_in_bounds(tl, en, ty)) return fail(LBM_MS_E_ARG, "work list out of bounds");
         int rc = hip(hipMemcpyAsync(ws + L.tiles, tl.data(), tl.size() * sizeof(int4),
                                     hipMemcpyHostToDevice, stream), "tile upload");
         if (rc) return rc;
@@ -319,6 +321,7 @@ long long build_index(const std::vector<uint8_t>& solid, std::vector<int32_t>& i
 // nodes whose moments its gradients read (halo: axis neighbours of own nodes, including rows
 // past the end of the box, which hold the periodic image).  Entries are moment-tile coordinates
 // (cx, cy) = (x - x0 + 1, y - y0 + 1) packed as cy << 8 | cx.  Tiles without fluid are dropped.
+// Entry offsets are ent_base + the position in ent (several instances may append to one ent).
 void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, int instance,
                     uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent)
 {
@@ -360,6 +363,25 @@ void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, i
             tiles.push_back(make_int4(x0, y0, instance, 0));
             tiles.push_back(make_int4((int)own_off, (int)own_cnt, (int)halo_off, (int)halo_cnt));
         }
+}
+
+// Every tile's entry ranges lie inside the entry array and every entry inside the moment tile.
+bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>& ent, int ty)
+{
+    const size_t n_ent = ent.size();
+    for (size_t t = 0; t + 1 < tiles.size(); t += 2) {
+        const int4 r = tiles[t + 1];
+        if (r.x < 0 || r.y < 0 || r.z < 0 || r.w < 0) return false;
+        if ((size_t)r.x + (size_t)r.y > n_ent || (size_t)r.z + (size_t)r.w > n_ent) return false;
+        if (r.y > 2 * 32 * ty) return false;  // a lane holds at most two own nodes
+        for (int e = 0; e < r.y + r.w; ++e) {
+            const uint32_t v = ent[e < r.y ? (size_t)r.x + e : (size_t)r.z + (e - r.y)];
+            const uint32_t cx = v & 255u, cy = v >> 8;
+            if (cx > 65u || cy > (uint32_t)ty + 1u) return false;
+            if (e < r.y && (cx < 1u || cx > 64u || cy < 1u || cy > (uint32_t)ty)) return false;
+        }
+    }
+    return true;
 }
 
 int default_tile_y(const lbm_ms_params& p)
@@ -926,6 +948,428 @@ int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info)
     info->chunk_z = h->cz;
     info->workspace_bytes = h->L.total;
     return LBM_MS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// batched solves
+// ---------------------------------------------------------------------------------------------
+struct lbm_ms_batch_s {
+    lbm_ms_params common{};
+    hipStream_t user = nullptr;  // caller's stream
+    hipStream_t stream = nullptr;  // the batch's own stream (graph capture needs a non-legacy one)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<lbm_ms_s*> inst;
+    std::vector<std::vector<int4>> tiles_k;
+    char* ws = nullptr;
+    size_t off_tab = 0, off_tiles = 0, off_ent = 0;
+    size_t tile_cap = 0, ent_cap = 0;
+    int count = 0, ty = 0;
+    std::vector<char> active;
+    int ntiles = 0;
+    int cur = 0;
+    bool use_graphs = true;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_len = 0;
+    std::string err;
+
+    int fail(int code, const std::string& m) { err = m; return code; }
+    int hip(hipError_t e, const char* what)
+    {
+        if (e == hipSuccess) return LBM_MS_OK;
+        return fail(LBM_MS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    // order the batch stream after the caller's stream
+    int enter()
+    {
+        int rc = hip(hipEventRecord(ev_in, user), "event record");
+        if (rc) return rc;
+        return hip(hipStreamWaitEvent(stream, ev_in, 0), "stream wait");
+    }
+    // order the caller's stream after the batch stream
+    int leave(int rc)
+    {
+        if (hipEventRecord(ev_out, stream) == hipSuccess) (void)hipStreamWaitEvent(user, ev_out, 0);
+        return rc;
+    }
+    void drop_graphs()
+    {
+        for (auto& g : gexec)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+        graph_len = 0;
+    }
+    int upload_tables()
+    {
+        std::vector<StepArgs> t(2 * (size_t)count);
+        for (int k = 0; k < count; ++k) {
+            t[k] = inst[k]->args(0);
+            t[count + k] = inst[k]->args(1);
+        }
+        int rc = hip(hipStreamSynchronize(stream), "sync");
+        if (rc) return rc;
+        rc = hip(hipMemcpy(ws + off_tab, t.data(), t.size() * sizeof(StepArgs), hipMemcpyHostToDevice),
+                 "instance table upload");
+        return rc;
+    }
+    // work list of the active instances (host compaction of the per-instance tile lists)
+    int upload_active_tiles()
+    {
+        std::vector<int4> tl;
+        for (int k = 0; k < count; ++k)
+            if (active[k]) tl.insert(tl.end(), tiles_k[k].begin(), tiles_k[k].end());
+        if (tl.size() / 2 > tile_cap) return fail(LBM_MS_E_NOMEM, "tile list exceeds its share");
+        int rc = hip(hipStreamSynchronize(stream), "sync");
+        if (rc) return rc;
+        if (!tl.empty()) {
+            rc = hip(hipMemcpy(ws + off_tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice),
+                     "tile upload");
+            if (rc) return rc;
+        }
+        ntiles = (int)(tl.size() / 2);
+        drop_graphs();
+        return LBM_MS_OK;
+    }
+    int upload_lists()
+    {
+        std::vector<uint32_t> en;
+        tiles_k.assign(count, {});
+        for (int k = 0; k < count; ++k)
+            build_tiles_2d(inst[k]->p.nx, inst[k]->p.ny, ty, inst[k]->mask, k, 0, tiles_k[k], en);
+        if (en.size() > ent_cap) return fail(LBM_MS_E_NOMEM, "entry list exceeds its share");
+        for (int k = 0; k < count; ++k)
+            if (!tiles_in_bounds(tiles_k[k], en, ty))
+                return fail(LBM_MS_E_ARG, "work list of instance " + std::to_string(k) + " out of bounds");
+        int rc = hip(hipStreamSynchronize(stream), "sync");
+        if (rc) return rc;
+        rc = hip(hipMemcpy(ws + off_ent, en.data(), en.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                 "entry upload");
+        if (rc) return rc;
+        return upload_active_tiles();
+    }
+    hipError_t launch_one()
+    {
+        const StepArgs* tab = reinterpret_cast<const StepArgs*>(ws + off_tab) + (size_t)cur * count;
+        return launch_step2d(stream, tab, reinterpret_cast<const int4*>(ws + off_tiles),
+                             reinterpret_cast<const unsigned*>(ws + off_ent), ntiles,
+                             common.precision, node_shift(common) ? 1 : 0, ty);
+    }
+    void advance(int64_t n)
+    {
+        if (n & 1) cur ^= 1;
+        for (int k = 0; k < count; ++k)
+            if (active[k]) {
+                inst[k]->cur = cur;
+                inst[k]->steps += n;
+            }
+    }
+    int step_eager(int64_t n)
+    {
+        for (int64_t t = 0; t < n; ++t) {
+            const hipError_t e = launch_one();
+            if (e != hipSuccess) return hip(e, "batched step");
+            cur ^= 1;
+        }
+        if (n & 1) cur ^= 1;  // advance() applies the parity change once
+        advance(n);
+        return LBM_MS_OK;
+    }
+    // n steps as one hipGraph (captured once per start parity, active set and length)
+    int step_graph(int n)
+    {
+        if (graph_len != n) drop_graphs();
+        const int p0 = cur;
+        if (!gexec[p0]) {
+            hipGraph_t g = nullptr;
+            int rc = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+            if (rc) return rc;
+            hipError_t le = hipSuccess;
+            for (int t = 0; t < n && le == hipSuccess; ++t) {
+                le = launch_one();
+                cur ^= 1;
+            }
+            cur = p0;
+            const hipError_t ce = hipStreamEndCapture(stream, &g);
+            if (le != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip(le, "captured launch"); }
+            rc = hip(ce, "end capture");
+            if (rc) return rc;
+            rc = hip(hipGraphInstantiate(&gexec[p0], g, nullptr, nullptr, 0), "graph instantiate");
+            (void)hipGraphDestroy(g);
+            if (rc) return rc;
+            graph_len = n;
+        }
+        int rc = hip(hipGraphLaunch(gexec[p0], stream), "graph launch");
+        if (rc) return rc;
+        advance(n);
+        return LBM_MS_OK;
+    }
+};
+
+namespace {
+
+size_t instance_bytes(const lbm_ms_params& common, const lbm_ms_instance_desc& d, lbm_ms_params* out)
+{
+    lbm_ms_params p = common;
+    p.nx = d.nx;
+    p.ny = d.ny;
+    p.nz = 1;
+    if (out) *out = p;
+    return lbm_ms_workspace_bytes(&p);
+}
+
+bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
+                  std::vector<size_t>* offs, size_t* off_tab, size_t* off_tiles, size_t* off_ent,
+                  size_t* tile_cap, size_t* ent_cap, size_t* total)
+{
+    if (!common || !inst || count <= 0 || common->lattice != LBM_MS_D2Q9) return false;
+    size_t off = 0, tc = 0, ec = 0;
+    auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
+    if (offs) offs->clear();
+    for (int k = 0; k < count; ++k) {
+        const size_t b = instance_bytes(*common, inst[k], nullptr);
+        if (b == 0 || !inst[k].solid) return false;
+        const size_t o = take(b);
+        if (offs) offs->push_back(o);
+        tc += (size_t)((inst[k].nx + 63) / 64) * (size_t)((inst[k].ny + 3) / 4);
+        ec += 3ull * inst[k].nx * inst[k].ny + 4096;
+    }
+    const size_t ot = take(2ull * count * sizeof(StepArgs));
+    const size_t oti = take(tc * 2 * sizeof(int4));
+    const size_t oe = take(ec * sizeof(uint32_t));
+    if (off_tab) *off_tab = ot;
+    if (off_tiles) *off_tiles = oti;
+    if (off_ent) *off_ent = oe;
+    if (tile_cap) *tile_cap = tc;
+    if (ent_cap) *ent_cap = ec;
+    if (total) *total = off;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_ms_batch_workspace_bytes(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
+                                    int count)
+{
+    size_t total = 0;
+    if (!batch_layout(common, inst, count, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &total))
+        return 0;
+    return total;
+}
+
+void lbm_ms_batch_destroy(lbm_ms_batch_t b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    b->drop_graphs();
+    for (auto* h : b->inst) lbm_ms_destroy(h);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
+                        void* d_workspace, size_t bytes, lbm_ms_batch_t* out)
+{
+    if (!out) return LBM_MS_E_ARG;
+    *out = nullptr;
+    std::vector<size_t> offs;
+    size_t ot, oti, oe, tc, ec, total;
+    if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &tc, &ec, &total)) return LBM_MS_E_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return LBM_MS_E_ARG;
+    if (bytes < total) return LBM_MS_E_NOMEM;
+    lbm_ms_batch_s* b = new (std::nothrow) lbm_ms_batch_s();
+    if (!b) return LBM_MS_E_NOMEM;
+    b->common = *common;
+    b->user = (hipStream_t)common->stream;
+    b->ws = (char*)d_workspace;
+    b->off_tab = ot;
+    b->off_tiles = oti;
+    b->off_ent = oe;
+    b->tile_cap = tc;
+    b->ent_cap = ec;
+    b->count = count;
+    b->ty = default_tile_y(*common);
+    if (b->ty > 16 || !tile_ok(LBM_MS_D2Q9, b->ty, 0)) b->ty = 8;
+    int rc = LBM_MS_OK;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        lbm_ms_batch_destroy(b);
+        return LBM_MS_E_HIP;
+    }
+    rc = b->enter();
+    for (int k = 0; k < count && rc == LBM_MS_OK; ++k) {
+        lbm_ms_params pk;
+        const size_t bk = instance_bytes(*common, inst[k], &pk);
+        pk.stream = b->stream;
+        pk.tile_y = b->ty;
+        lbm_ms_t h = nullptr;
+        rc = lbm_ms_create(&pk, b->ws + offs[k], bk, &h);
+        if (rc) { b->err = "instance " + std::to_string(k) + ": create failed"; break; }
+        b->inst.push_back(h);
+        rc = lbm_ms_set_geometry(h, inst[k].solid);
+        if (rc == LBM_MS_OK) rc = lbm_ms_set_bc(h, inst[k].X_in, inst[k].j_A_per_m2);
+        if (rc) b->err = "instance " + std::to_string(k) + ": " + h->err;
+    }
+    if (rc == LBM_MS_OK) {
+        b->active.assign(count, 1);
+        rc = b->upload_lists();
+    }
+    if (rc == LBM_MS_OK) rc = b->upload_tables();
+    if (rc) {
+        const std::string e = b->err;
+        lbm_ms_batch_destroy(b);
+        (void)e;
+        return rc;
+    }
+    *out = b;
+    return b->leave(LBM_MS_OK);
+}
+
+const char* lbm_ms_batch_last_error(lbm_ms_batch_t b) { return b ? b->err.c_str() : "null batch"; }
+
+lbm_ms_t lbm_ms_batch_instance(lbm_ms_batch_t b, int k)
+{
+    if (!b || k < 0 || k >= b->count) return nullptr;
+    return b->inst[k];
+}
+
+int lbm_ms_batch_stats(lbm_ms_batch_t b, int* active, int64_t* fluid, int* tiles)
+{
+    if (!b) return LBM_MS_E_ARG;
+    int a = 0;
+    int64_t nf = 0;
+    for (int k = 0; k < b->count; ++k)
+        if (b->active[k]) { ++a; nf += b->inst[k]->n_fluid; }
+    if (active) *active = a;
+    if (fluid) *fluid = nf;
+    if (tiles) *tiles = b->ntiles;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y)
+{
+    if (!b) return LBM_MS_E_ARG;
+    if (!tile_ok(LBM_MS_D2Q9, tile_y, 0)) return b->fail(LBM_MS_E_ARG, "launch shape not compiled");
+    int rc = b->enter();
+    if (rc) return rc;
+    b->ty = tile_y;
+    for (auto* h : b->inst) h->ty = tile_y;
+    rc = b->upload_lists();
+    return b->leave(rc);
+}
+
+int lbm_ms_batch_use_graphs(lbm_ms_batch_t b, int enable)
+{
+    if (!b) return LBM_MS_E_ARG;
+    b->use_graphs = enable != 0;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device)
+{
+    if (!b) return LBM_MS_E_ARG;
+    int rc = b->enter();
+    if (rc) return rc;
+    size_t off = 0;
+    for (int k = 0; k < b->count && rc == LBM_MS_OK; ++k) {
+        lbm_ms_t h = b->inst[k];
+        rc = lbm_ms_init(h, X0 ? X0 + off : nullptr, on_device);
+        if (rc) b->err = "instance " + std::to_string(k) + ": " + h->err;
+        off += 3ull * h->N;
+    }
+    if (rc == LBM_MS_OK) {
+        b->cur = 0;
+        b->active.assign(b->count, 1);
+        rc = b->upload_active_tiles();
+    }
+    return b->leave(rc);
+}
+
+int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return LBM_MS_E_ARG;
+    for (auto* h : b->inst)
+        if (!h->ready) return b->fail(LBM_MS_E_STATE, "init first");
+    int rc = b->enter();
+    if (rc) return rc;
+    rc = b->step_eager(nsteps);
+    return b->leave(rc);
+}
+
+int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int check_every,
+                          int64_t* steps_taken, double* residual)
+{
+    if (!b || check_every <= 0 || max_steps < 0) return LBM_MS_E_ARG;
+    for (auto* h : b->inst)
+        if (!h->ready) return b->fail(LBM_MS_E_STATE, "init first");
+    int rc = b->enter();
+    if (rc) return rc;
+    std::vector<int64_t> taken_k(b->count, 0);
+    std::vector<double> r_k(b->count, INFINITY);
+    // fresh residual windows
+    for (int k = 0; k < b->count && rc == LBM_MS_OK; ++k) {
+        if (!b->active[k]) continue;
+        double v[6];
+        rc = reduce_state(b->inst[k], 1, v);
+        b->inst[k]->snap_step = b->inst[k]->steps;
+    }
+    int64_t taken = 0;
+    bool changed = false;
+    while (rc == LBM_MS_OK && taken < max_steps) {
+        int n_active = 0;
+        for (int k = 0; k < b->count; ++k) n_active += b->active[k];
+        if (n_active == 0) break;
+        if (changed) {
+            rc = b->upload_active_tiles();
+            if (rc) break;
+            changed = false;
+        }
+        const int64_t n = std::min<int64_t>(check_every, max_steps - taken);
+        rc = (b->use_graphs && n == check_every) ? b->step_graph((int)n) : b->step_eager(n);
+        if (rc) break;
+        taken += n;
+        for (int k = 0; k < b->count; ++k) {
+            if (!b->active[k]) continue;
+            double r = 0;
+            const int rk = lbm_ms_residual(b->inst[k], &r);
+            taken_k[k] = taken;
+            r_k[k] = r;
+            if (rk) {
+                rc = rk;
+                b->err = "instance " + std::to_string(k) + ": " + b->inst[k]->err;
+                break;
+            }
+            if (r < tol) {
+                b->active[k] = 0;
+                changed = true;
+            }
+        }
+    }
+    if (steps_taken) std::memcpy(steps_taken, taken_k.data(), sizeof(int64_t) * b->count);
+    if (residual) std::memcpy(residual, r_k.data(), sizeof(double) * b->count);
+    if (rc == LBM_MS_OK) {
+        for (int k = 0; k < b->count; ++k)
+            if (!(r_k[k] < tol)) {
+                rc = b->fail(LBM_MS_E_NOT_CONVERGED, "instance " + std::to_string(k) + " not converged");
+                break;
+            }
+    }
+    return b->leave(rc);
+}
+
+int lbm_ms_batch_overpotential(lbm_ms_batch_t b, double* eta)
+{
+    if (!b || !eta) return LBM_MS_E_ARG;
+    int rc = b->enter();
+    for (int k = 0; k < b->count && rc == LBM_MS_OK; ++k) {
+        rc = lbm_ms_overpotential(b->inst[k], &eta[k]);
+        if (rc) b->err = "instance " + std::to_string(k) + ": " + b->inst[k]->err;
+    }
+    return b->leave(rc);
 }
 
 }  // extern "C"

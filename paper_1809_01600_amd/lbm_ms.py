@@ -68,6 +68,15 @@ class lbm_ms_info(ctypes.Structure):
     ]
 
 
+class lbm_ms_instance_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("solid", ctypes.POINTER(ctypes.c_uint8)),
+        ("X_in", ctypes.c_double * 3),
+        ("j_A_per_m2", ctypes.c_double),
+    ]
+
+
 class LbmMsError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("lbm_ms status %d: %s" % (status, message))
@@ -107,6 +116,25 @@ _SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     ("lbm_ms_set_tile", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
+    ("lbm_ms_batch_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(lbm_ms_params),
+                                                     ctypes.POINTER(lbm_ms_instance_desc),
+                                                     ctypes.c_int]),
+    ("lbm_ms_batch_create", ctypes.c_int, [ctypes.POINTER(lbm_ms_params),
+                                           ctypes.POINTER(lbm_ms_instance_desc), ctypes.c_int,
+                                           _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    ("lbm_ms_batch_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
+    ("lbm_ms_batch_step", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("lbm_ms_batch_converge", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int64), _DP]),
+    ("lbm_ms_batch_overpotential", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_batch_instance", _VP, [_VP, ctypes.c_int]),
+    ("lbm_ms_batch_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int)]),
+    ("lbm_ms_batch_set_tile", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lbm_ms_batch_use_graphs", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lbm_ms_batch_last_error", ctypes.c_char_p, [_VP]),
+    ("lbm_ms_batch_destroy", None, [_VP]),
     ("lbm_ms_last_error", ctypes.c_char_p, [_VP]),
     ("lbm_ms_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("lbm_ms_destroy", None, [_VP]),
@@ -331,3 +359,118 @@ class Solver:
 
     def set_tile(self, tile_y: int, chunk_z: int = 0):
         self._check(lib().lbm_ms_set_tile(self.h, tile_y, chunk_z))
+
+
+class _InstanceView(Solver):
+    """A batch member: the single-instance calls on a handle the batch owns."""
+
+    def __init__(self, batch, k, case):  # noqa: D401  (no workspace of its own)
+        self.case = case
+        self.h = lib().lbm_ms_batch_instance(batch.b, k)
+        self._batch = batch
+        self.N = case.nx * case.ny * case.nz
+        self.q = 9
+
+    def close(self):
+        self.h = None  # owned by the batch
+
+
+class Batch:
+    """Many D2Q9 problems advanced by one launch per step (see lbm_ms_batch_* in lbm_ms.h)."""
+
+    def __init__(self, cases, precision="fp32", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
+                 tile_y=0, eps_flux=-1.0, device="cuda"):
+        import torch
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.cases = list(cases)
+        c0 = self.cases[0]
+        shared = ("lattice", "T", "p", "D12", "D13", "D23", "dx", "tau_ref", "nu", "n_electrons")
+        for c in self.cases[1:]:
+            for f in shared:
+                if getattr(c, f) != getattr(c0, f):
+                    raise ValueError("batch members must share %s" % f)
+        if c0.lattice != "D2Q9" or any(c.nz != 1 for c in self.cases):
+            raise ValueError("batched solves are two-dimensional (D2Q9)")
+        self.stream = torch.cuda.current_stream(torch.device(device))
+        self.params = make_params(c0, precision, shift_mode, ms_mode, INLET_DIRICHLET, eps_flux,
+                                  0.0, 0.0, tile_y, 0, self.stream.cuda_stream)
+        n = len(self.cases)
+        self._masks = [np.ascontiguousarray(c.mask(), dtype=np.uint8).reshape(-1) for c in self.cases]
+        self.desc = (lbm_ms_instance_desc * n)()
+        for k, c in enumerate(self.cases):
+            d = self.desc[k]
+            d.nx, d.ny = c.nx, c.ny
+            d.solid = self._masks[k].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            for s_ in range(3):
+                d.X_in[s_] = c.X_in[s_]
+            d.j_A_per_m2 = c.j_A_m2
+        nbytes = lib().lbm_ms_batch_workspace_bytes(ctypes.byref(self.params), self.desc, n)
+        if nbytes == 0:
+            raise LbmMsError(E_ARG, "invalid batch parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=torch.device(device))
+        b = _VP()
+        rc = lib().lbm_ms_batch_create(ctypes.byref(self.params), self.desc, n,
+                                       ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       ctypes.byref(b))
+        if rc != OK:
+            raise LbmMsError(rc, lib().lbm_ms_status_string(rc).decode())
+        self.b = b
+        self.count = n
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmMsError(rc, lib().lbm_ms_status_string(rc).decode() + ": " +
+                             lib().lbm_ms_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().lbm_ms_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, X0=None):
+        if X0 is None:
+            self._check(lib().lbm_ms_batch_init(self.b, None, 0))
+        elif hasattr(X0, "data_ptr"):
+            self._check(lib().lbm_ms_batch_init(self.b, ctypes.c_void_p(X0.data_ptr()), 1))
+        else:
+            a = np.ascontiguousarray(X0, dtype=np.float64).reshape(-1)
+            self._check(lib().lbm_ms_batch_init(self.b, a.ctypes.data_as(_VP), 0))
+
+    def step(self, n=1):
+        self._check(lib().lbm_ms_batch_step(self.b, int(n)))
+
+    def converge(self, tol, max_steps, check_every=100, raise_on_fail=True):
+        steps = (ctypes.c_int64 * self.count)()
+        r = (ctypes.c_double * self.count)()
+        rc = lib().lbm_ms_batch_converge(self.b, tol, int(max_steps), int(check_every), steps, r)
+        if raise_on_fail:
+            self._check(rc)
+        return np.array(steps[:], dtype=np.int64), np.array(r[:]), rc
+
+    def overpotential(self):
+        eta = np.zeros(self.count)
+        self._check(lib().lbm_ms_batch_overpotential(self.b, _dp(eta)))
+        return eta
+
+    def instance(self, k) -> Solver:
+        return _InstanceView(self, k, self.cases[k])
+
+    def stats(self):
+        a = ctypes.c_int(0)
+        nf = ctypes.c_int64(0)
+        t = ctypes.c_int(0)
+        self._check(lib().lbm_ms_batch_stats(self.b, ctypes.byref(a), ctypes.byref(nf), ctypes.byref(t)))
+        return a.value, nf.value, t.value
+
+    def set_tile(self, tile_y):
+        self._check(lib().lbm_ms_batch_set_tile(self.b, int(tile_y)))
+
+    def use_graphs(self, enable=True):
+        self._check(lib().lbm_ms_batch_use_graphs(self.b, 1 if enable else 0))
