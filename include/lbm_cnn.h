@@ -1,0 +1,81 @@
+/*
+ * lbm_cnn.h - C ABI of the HIP (gfx950) kernels of the learned warm start: a small convolutional
+ * network (3x3 convolutions, ReLU) that maps a porous slice, its inlet composition and current
+ * density to an initial mole-fraction field for the LBM / Maxwell-Stefan solver.  The method's
+ * own steady fields are the training targets; the solver then converges from the prediction.
+ *
+ * Conventions: tensors are NCHW float32 (or bfloat16 where named), contiguous, device memory
+ * owned by the caller; every call is enqueued on `stream` (hipStream_t) and returns 0 or a
+ * negative lbm_ms_status code (-1 invalid argument, -4 HIP error).  Convolutions use zero
+ * padding of one pixel, so output and input have the same H x W.  Channel counts: C_in <= 32,
+ * C_out <= 32.  Weights are [C_out][C_in][3][3], biases [C_out].
+ */
+#ifndef LBM_CNN_H
+#define LBM_CNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out = act(conv3x3(in * gate, w) + b), act = ReLU if relu != 0.  gate (may be NULL) multiplies
+ * each input value by (gate > 0) with gate shaped like in (used to apply a ReLU derivative). */
+int lbm_cnn_conv_forward(const float* in, const float* gate, int B, int C_in, int H, int W,
+                         const float* w, const float* b, int C_out, int relu, float* out,
+                         void* stream);
+
+/* Same convolution with bfloat16 activations and weights (raw uint16 bit patterns), FP32
+ * accumulation; b stays float32. */
+int lbm_cnn_conv_forward_bf16(const uint16_t* in, int B, int C_in, int H, int W,
+                              const uint16_t* w, const float* b, int C_out, int relu,
+                              uint16_t* out, void* stream);
+
+/* Gradient of the input of a convolution layer: grad_in = conv3x3(grad_out * (act > 0), w^T)
+ * with w^T the transposed, flipped kernel (act = the layer's output if it has a ReLU, else NULL).
+ * wt_scratch: C_in*C_out*9 floats. */
+int lbm_cnn_conv_backward_data(const float* grad_out, const float* act, int B, int C_out, int H,
+                               int W, const float* w, int C_in, float* grad_in, float* wt_scratch,
+                               void* stream);
+
+/* Gradients of weights and bias: grad_w = sum over images and pixels of (grad_out * (act > 0)) x
+ * im2col(in), grad_b = sum of (grad_out * (act > 0)).  Deterministic: per-workgroup partial sums
+ * in partial (at least lbm_cnn_backward_weight_scratch floats), then a fixed-order sum. */
+size_t lbm_cnn_backward_weight_scratch(int B, int C_in, int C_out, int H, int W);
+int lbm_cnn_conv_backward_weight(const float* in, const float* grad_out, const float* act, int B,
+                                 int C_in, int C_out, int H, int W, float* grad_w, float* grad_b,
+                                 float* partial, void* stream);
+
+/* Masked mean squared error over fluid pixels: loss = sum m (p - t)^2 / (C sum m), with m =
+ * fluid[B][H][W] (1 fluid, 0 solid); grad = d loss / d pred.  loss_out: one float64 on the
+ * device; partial: 2 * 1024 + 1 float64 scratch. */
+int lbm_cnn_masked_mse(const float* pred, const float* target, const float* fluid, int B, int C,
+                       int H, int W, float* grad, double* loss_out, double* partial,
+                       void* stream);
+
+/* Adam update of n parameters (step t >= 1). */
+int lbm_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int t, void* stream);
+
+/* float32 -> bfloat16 (round to nearest even) bit patterns. */
+int lbm_cnn_to_bf16(const float* in, uint16_t* out, int64_t n, void* stream);
+int lbm_cnn_from_bf16(const uint16_t* in, float* out, int64_t n, void* stream);
+
+/* Input features [B][8][H][W]: fluid indicator, the inlet mole fractions X_in[B][3] broadcast,
+ * j[B] (A/cm^2) / 2, x / (W - 1), and the paper's one-dimensional profile prof[B][2][W] (X_1,
+ * X_2 along x) broadcast over y.  solid: [B][H][W] uint8. */
+int lbm_cnn_features(const uint8_t* solid, const double* X_in, const double* j_A_cm2,
+                     const double* prof, int B, int H, int W, float* feat, void* stream);
+
+/* Initial field from a prediction pred[B][2][H][W]: X_s = prof_s + scale * pred_s (s = 1, 2),
+ * each at least x_min, X_3 = 1 - X_1 - X_2 at least x_min (renormalized), written as
+ * X[B][3][H][W] float64 (the layout lbm_ms_init / lbm_ms_batch_init take). */
+int lbm_cnn_assemble(const float* pred, const double* prof, int B, int H, int W, float scale,
+                     double x_min, double* X, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_CNN_H */

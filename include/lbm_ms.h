@@ -119,6 +119,11 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
  * In LBM_MS_INLET_WALL mode the mask is used as given. */
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
 
+/* The same clean-up on the host only (no device, no handle): solid_out = cleaned mask,
+ * *n_open = fluid nodes left in the outlet column (0: the outlet is unreachable). */
+int lbm_ms_clean_geometry(int lattice, int nx, int ny, int nz, const uint8_t* solid_in,
+                          uint8_t* solid_out, int64_t* n_open);
+
 /* Cleaned mask (after set_geometry) copied to a host buffer of nx*ny*nz bytes. */
 int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host);
 
@@ -138,6 +143,10 @@ int lbm_ms_init(lbm_ms_t h, const double* X0, int x0_on_device);
  * generalized Fick law (Eq. 31, Gamma = I) is integrated from the inlet composition; the 1D
  * profile is copied over y and z.  Uses the superficial flux (no open-area scaling). */
 int lbm_ms_init_paper_profile(lbm_ms_t h);
+
+/* The one-dimensional profile behind lbm_ms_init_paper_profile, prof[2][nx] (X_1, X_2 at the
+ * node columns x = 0 .. nx - 1), copied to host memory.  Does not change the state. */
+int lbm_ms_paper_profile(lbm_ms_t h, double* prof_host);
 
 /* nsteps time steps, enqueued on the stream (asynchronous). */
 int lbm_ms_step(lbm_ms_t h, int64_t nsteps);
@@ -230,10 +239,15 @@ int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device);
 int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps);
 
 /* Steps in hipGraph-captured chunks of check_every until every instance's residual (as
- * lbm_ms_residual) is below tol or max_steps is reached.  steps_taken[k], residual[k] per
- * instance (may be NULL).  Returns E_NOT_CONVERGED if any instance did not converge. */
+ * lbm_ms_residual) is below tol or max_steps is reached.  An instance whose check fails
+ * (E_NEG_FRACTION when its current exceeds what its pores can supply, E_DIVERGED, E_TAU_CLAMP)
+ * retires with that status while the others go on.  Per instance (each pointer may be NULL):
+ * steps_taken[k], residual[k], status[k] (0 = converged, E_NOT_CONVERGED, or the failure).
+ * Retired instances stay out of the work list (and report their retirement status, 0 steps and
+ * residual +inf in later calls) until lbm_ms_batch_init.
+ * Returns 0 if every instance converged, else the first nonzero status in instance order. */
 int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int check_every,
-                          int64_t* steps_taken, double* residual);
+                          int64_t* steps_taken, double* residual, int* status);
 
 /* Per-instance overpotential (Eq. 43) into eta[count]. */
 int lbm_ms_batch_overpotential(lbm_ms_batch_t b, double* eta);

@@ -1,0 +1,474 @@
+// HIP kernels (gfx950) of the learned warm start: 3x3 convolution forward / backward, masked MSE,
+// Adam, and the feature / assembly kernels that connect the network to the LBM solver.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "lbm_cnn.h"
+
+namespace lbmcnn {
+
+constexpr int TS = 16;         // output tile edge (pixels); workgroup = TS x TS lanes
+constexpr int HALO = TS + 2;   // input tile edge
+constexpr int CCH = 8;         // input channels staged per pass
+constexpr int MAXC = 32;       // largest channel count
+constexpr int WG_PARTIALS = 1024;  // upper bound on backward-weight workgroups
+
+__device__ inline float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// round to nearest even
+__device__ inline uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <class T> __device__ inline float ld(const T* p, long long i);
+template <> __device__ inline float ld<float>(const float* p, long long i) { return p[i]; }
+template <> __device__ inline float ld<uint16_t>(const uint16_t* p, long long i) { return bf16_to_f32(p[i]); }
+template <class T> __device__ inline void st(T* p, long long i, float v);
+template <> __device__ inline void st<float>(float* p, long long i, float v) { p[i] = v; }
+template <> __device__ inline void st<uint16_t>(uint16_t* p, long long i, float v) { p[i] = f32_to_bf16(v); }
+
+// out[b][co][y][x] = act(bias[co] + sum_ci sum_k w[co][ci][k] * in'[b][ci][y+ky-1][x+kx-1]),
+// in' = in * (gate > 0) when gate is given.  One workgroup = one 16x16 tile of one image, all
+// output channels per lane (COUT accumulators); weights in LDS (broadcast reads).
+template <class T, class WT, int COUT>
+__global__ __launch_bounds__(TS * TS) void k_conv_fwd(const T* __restrict__ in,
+                                                      const float* __restrict__ gate, int Cin,
+                                                      int H, int W, const WT* __restrict__ w,
+                                                      const float* __restrict__ bias, int relu,
+                                                      T* __restrict__ out)
+{
+    __shared__ float sW[COUT * MAXC * 9];
+    __shared__ float sIn[CCH][HALO][HALO];
+    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+    const int x = blockIdx.x * TS + tx, y = blockIdx.y * TS + ty;
+    const int b = blockIdx.z;
+    const long long plane = (long long)H * W;
+    for (int i = threadIdx.x; i < COUT * Cin * 9; i += TS * TS) sW[i] = ld<WT>(w, i);
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = bias ? bias[co] : 0.f;
+    for (int c0 = 0; c0 < Cin; c0 += CCH) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < CCH * HALO * HALO; i += TS * TS) {
+            const int c = i / (HALO * HALO), r = i % (HALO * HALO);
+            const int gy = blockIdx.y * TS + r / HALO - 1, gx = blockIdx.x * TS + r % HALO - 1;
+            float v = 0.f;
+            if (c0 + c < Cin && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const long long gi = ((long long)b * Cin + c0 + c) * plane + (long long)gy * W + gx;
+                v = ld<T>(in, gi);
+                if (gate && !(gate[gi] > 0.f)) v = 0.f;
+            }
+            sIn[c][r / HALO][r % HALO] = v;
+        }
+        __syncthreads();
+        const int cn = min(CCH, Cin - c0);
+        for (int c = 0; c < cn; ++c)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float v = sIn[c][ty + k / 3][tx + k % 3];
+                const float* wk = &sW[(c0 + c) * 9 + k];
+#pragma unroll
+                for (int co = 0; co < COUT; ++co) acc[co] += wk[co * Cin * 9] * v;
+            }
+    }
+    if (x < W && y < H) {
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) {
+            float o = acc[co];
+            if (relu) o = o > 0.f ? o : 0.f;
+            st<T>(out, ((long long)b * COUT + co) * plane + (long long)y * W + x, o);
+        }
+    }
+}
+
+// w^T[ci][co][8 - k] = w[co][ci][k]
+__global__ void k_transpose_flip(const float* __restrict__ w, int Cout, int Cin, float* __restrict__ wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Cout * Cin * 9) return;
+    const int k = i % 9, ci = (i / 9) % Cin, co = i / (9 * Cin);
+    wt[(ci * Cout + co) * 9 + (8 - k)] = w[i];
+}
+
+// Per-workgroup partial sums of grad_w[co][ci][k] and grad_b[co] over a run of 16x16 tiles.
+// Lane t owns up to four (co, ci) pairs (all nine taps each); lanes < Cout also sum the bias.
+__global__ __launch_bounds__(TS * TS) void k_conv_bwd_w(const float* __restrict__ in,
+                                                        const float* __restrict__ go,
+                                                        const float* __restrict__ act, int B,
+                                                        int Cin, int Cout, int H, int W,
+                                                        int tiles_per_wg, float* __restrict__ partial)
+{
+    __shared__ float sGo[MAXC][TS * TS];
+    __shared__ float sIn[MAXC][HALO * HALO];
+    const int tilesx = (W + TS - 1) / TS, tilesy = (H + TS - 1) / TS;
+    const int ntiles = B * tilesx * tilesy;
+    const int npairs = Cout * Cin;
+    const long long plane = (long long)H * W;
+    float acc[4][9];
+    float accb = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[r][k] = 0.f;
+    const int t0 = blockIdx.x * tiles_per_wg;
+    for (int tt = t0; tt < min(t0 + tiles_per_wg, ntiles); ++tt) {
+        const int b = tt / (tilesx * tilesy);
+        const int rr = tt % (tilesx * tilesy);
+        const int bx = rr % tilesx, by = rr / tilesx;
+        __syncthreads();
+        for (int i = threadIdx.x; i < Cout * TS * TS; i += TS * TS) {
+            const int co = i / (TS * TS), p = i % (TS * TS);
+            const int gy = by * TS + p / TS, gx = bx * TS + p % TS;
+            float v = 0.f;
+            if (gy < H && gx < W) {
+                const long long gi = ((long long)b * Cout + co) * plane + (long long)gy * W + gx;
+                v = go[gi];
+                if (act && !(act[gi] > 0.f)) v = 0.f;
+            }
+            sGo[co][p] = v;
+        }
+        for (int i = threadIdx.x; i < Cin * HALO * HALO; i += TS * TS) {
+            const int c = i / (HALO * HALO), r = i % (HALO * HALO);
+            const int gy = by * TS + r / HALO - 1, gx = bx * TS + r % HALO - 1;
+            float v = 0.f;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                v = in[((long long)b * Cin + c) * plane + (long long)gy * W + gx];
+            sIn[c][r] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pr = threadIdx.x + r * TS * TS;
+            if (pr >= npairs) break;
+            const int co = pr / Cin, ci = pr % Cin;
+            for (int p = 0; p < TS * TS; ++p) {
+                const float g = sGo[co][p];
+                const int py = p / TS, px = p % TS;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) acc[r][k] += g * sIn[ci][(py + k / 3) * HALO + px + k % 3];
+            }
+        }
+        if (threadIdx.x < (unsigned)Cout)
+            for (int p = 0; p < TS * TS; ++p) accb += sGo[threadIdx.x][p];
+    }
+    float* out = partial + (long long)blockIdx.x * (npairs * 9 + Cout);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pr = threadIdx.x + r * TS * TS;
+        if (pr >= npairs) break;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[pr * 9 + k] = acc[r][k];
+    }
+    if (threadIdx.x < (unsigned)Cout) out[npairs * 9 + threadIdx.x] = accb;
+}
+
+// fixed-order sum of the per-workgroup partials
+__global__ void k_sum_partials(const float* __restrict__ partial, int nwg, int nw, int nb,
+                               float* __restrict__ gw, float* __restrict__ gb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw + nb) return;
+    float s = 0.f;
+    for (int g = 0; g < nwg; ++g) s += partial[(long long)g * (nw + nb) + i];
+    if (i < nw) gw[i] = s;
+    else gb[i - nw] = s;
+}
+
+// pass 1: unnormalized gradient 2 m (p - t) and per-workgroup sums of m (p - t)^2 and m
+__global__ __launch_bounds__(256) void k_masked_mse(const float* __restrict__ pred,
+                                                    const float* __restrict__ tgt,
+                                                    const float* __restrict__ fluid, int B, int C,
+                                                    int H, int W, float* __restrict__ grad,
+                                                    double* __restrict__ partial)
+{
+    __shared__ double red[2][4];
+    const long long plane = (long long)H * W;
+    const long long n = (long long)B * C * plane;
+    double se = 0.0, cnt = 0.0;
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const long long p = i % plane, b = i / (C * plane);
+        const float m = fluid[b * plane + p];
+        const float d = pred[i] - tgt[i];
+        se += (double)(m * d * d);
+        cnt += (double)m;
+        grad[i] = 2.f * m * d;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        se += __shfl_down(se, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = se;
+        red[1][threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        partial[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// pass 2 (one lane): loss = sum / count in fixed order; 1 / count for pass 3
+__global__ void k_mse_finalize(const double* __restrict__ partial, int nwg, double* __restrict__ loss,
+                               double* __restrict__ inv_count)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double se = 0.0, cnt = 0.0;
+    for (int g = 0; g < nwg; ++g) {
+        se += partial[2 * g];
+        cnt += partial[2 * g + 1];
+    }
+    loss[0] = cnt > 0 ? se / cnt : 0.0;
+    inv_count[0] = cnt > 0 ? 1.0 / cnt : 0.0;
+}
+
+// pass 3: grad /= count
+__global__ void k_scale(float* __restrict__ g, long long n, const double* __restrict__ s)
+{
+    const float f = (float)s[0];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        g[i] *= f;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = f32_to_bf16(in[i]);
+}
+
+__global__ void k_from_bf16(const uint16_t* __restrict__ in, float* __restrict__ out, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = bf16_to_f32(in[i]);
+}
+
+__global__ void k_features(const uint8_t* __restrict__ solid, const double* __restrict__ X_in,
+                           const double* __restrict__ j, const double* __restrict__ prof, int B,
+                           int H, int W, float* __restrict__ feat)
+{
+    const long long plane = (long long)H * W;
+    const long long n = (long long)B * plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long b = i / plane, p = i % plane;
+        const int x = (int)(p % W);
+        float* f = feat + b * 8 * plane + p;
+        f[0] = solid[i] ? 0.f : 1.f;
+        f[plane] = (float)X_in[3 * b];
+        f[2 * plane] = (float)X_in[3 * b + 1];
+        f[3 * plane] = (float)X_in[3 * b + 2];
+        f[4 * plane] = (float)(0.5 * j[b]);
+        f[5 * plane] = W > 1 ? (float)x / (float)(W - 1) : 0.f;
+        f[6 * plane] = (float)prof[(b * 2) * W + x];
+        f[7 * plane] = (float)prof[(b * 2 + 1) * W + x];
+    }
+}
+
+__global__ void k_assemble(const float* __restrict__ pred, const double* __restrict__ prof, int B,
+                           int H, int W, float scale, double x_min, double* __restrict__ X)
+{
+    const long long plane = (long long)H * W;
+    const long long n = (long long)B * plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long b = i / plane, p = i % plane;
+        const int x = (int)(p % W);
+        double x1 = prof[(b * 2) * W + x] + (double)scale * pred[(b * 2) * plane + p];
+        double x2 = prof[(b * 2 + 1) * W + x] + (double)scale * pred[(b * 2 + 1) * plane + p];
+        x1 = x1 > x_min ? x1 : x_min;
+        x2 = x2 > x_min ? x2 : x_min;
+        double x3 = 1.0 - x1 - x2;
+        if (x3 < x_min) {
+            const double s = (1.0 - x_min) / (x1 + x2);
+            x1 *= s;
+            x2 *= s;
+            x3 = 1.0 - x1 - x2;
+        }
+        X[(b * 3) * plane + p] = x1;
+        X[(b * 3 + 1) * plane + p] = x2;
+        X[(b * 3 + 2) * plane + p] = x3;
+    }
+}
+
+inline int grid_for(long long n, int bs = 256, int cap = 8192)
+{
+    long long g = (n + bs - 1) / bs;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+inline int status(hipError_t e) { return e == hipSuccess ? 0 : -4; }
+
+template <class T, class WT>
+int conv_forward(const T* in, const float* gate, int B, int Cin, int H, int W, const WT* w,
+                 const float* b, int Cout, int relu, T* out, hipStream_t st)
+{
+    if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || Cin <= 0 || Cin > MAXC) return -1;
+    const dim3 grid((W + TS - 1) / TS, (H + TS - 1) / TS, B);
+    switch (Cout) {
+    case 32: hipLaunchKernelGGL((k_conv_fwd<T, WT, 32>), grid, dim3(TS * TS), 0, st, in, gate, Cin, H, W, w, b, relu, out); break;
+    case 8: hipLaunchKernelGGL((k_conv_fwd<T, WT, 8>), grid, dim3(TS * TS), 0, st, in, gate, Cin, H, W, w, b, relu, out); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<T, WT, 2>), grid, dim3(TS * TS), 0, st, in, gate, Cin, H, W, w, b, relu, out); break;
+    default: return -1;
+    }
+    return status(hipGetLastError());
+}
+
+}  // namespace lbmcnn
+
+using namespace lbmcnn;
+
+extern "C" {
+
+int lbm_cnn_conv_forward(const float* in, const float* gate, int B, int C_in, int H, int W,
+                         const float* w, const float* b, int C_out, int relu, float* out,
+                         void* stream)
+{
+    return conv_forward<float, float>(in, gate, B, C_in, H, W, w, b, C_out, relu, out,
+                                      (hipStream_t)stream);
+}
+
+int lbm_cnn_conv_forward_bf16(const uint16_t* in, int B, int C_in, int H, int W,
+                              const uint16_t* w, const float* b, int C_out, int relu,
+                              uint16_t* out, void* stream)
+{
+    return conv_forward<uint16_t, uint16_t>(in, nullptr, B, C_in, H, W, w, b, C_out, relu, out,
+                                            (hipStream_t)stream);
+}
+
+int lbm_cnn_conv_backward_data(const float* grad_out, const float* act, int B, int C_out, int H,
+                               int W, const float* w, int C_in, float* grad_in, float* wt_scratch,
+                               void* stream)
+{
+    if (!grad_out || !w || !grad_in || !wt_scratch || C_out <= 0 || C_out > MAXC) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = C_out * C_in * 9;
+    hipLaunchKernelGGL(k_transpose_flip, dim3((n + 255) / 256), dim3(256), 0, st, w, C_out, C_in, wt_scratch);
+    const int e = status(hipGetLastError());
+    if (e) return e;
+    return conv_forward<float, float>(grad_out, act, B, C_out, H, W, wt_scratch, nullptr, C_in, 0,
+                                      grad_in, st);
+}
+
+static int bwd_w_groups(int B, int H, int W, int* tiles_per)
+{
+    const long long ntiles = (long long)B * ((W + TS - 1) / TS) * ((H + TS - 1) / TS);
+    const long long tp = (ntiles + WG_PARTIALS - 1) / WG_PARTIALS;
+    *tiles_per = (int)(tp < 1 ? 1 : tp);
+    return (int)((ntiles + *tiles_per - 1) / *tiles_per);
+}
+
+size_t lbm_cnn_backward_weight_scratch(int B, int C_in, int C_out, int H, int W)
+{
+    int tp;
+    const int nwg = bwd_w_groups(B, H, W, &tp);
+    return (size_t)nwg * (size_t)(C_out * C_in * 9 + C_out);
+}
+
+int lbm_cnn_conv_backward_weight(const float* in, const float* grad_out, const float* act, int B,
+                                 int C_in, int C_out, int H, int W, float* grad_w, float* grad_b,
+                                 float* partial, void* stream)
+{
+    if (!in || !grad_out || !grad_w || !grad_b || !partial) return -1;
+    if (C_in <= 0 || C_in > MAXC || C_out <= 0 || C_out > MAXC || C_in * C_out > 4 * TS * TS)
+        return -1;
+    hipStream_t st = (hipStream_t)stream;
+    int tp;
+    const int nwg = bwd_w_groups(B, H, W, &tp);
+    hipLaunchKernelGGL(k_conv_bwd_w, dim3(nwg), dim3(TS * TS), 0, st, in, grad_out, act, B, C_in,
+                       C_out, H, W, tp, partial);
+    int e = status(hipGetLastError());
+    if (e) return e;
+    const int nw = C_out * C_in * 9;
+    hipLaunchKernelGGL(k_sum_partials, dim3((nw + C_out + 255) / 256), dim3(256), 0, st, partial,
+                       nwg, nw, C_out, grad_w, grad_b);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_masked_mse(const float* pred, const float* target, const float* fluid, int B, int C,
+                       int H, int W, float* grad, double* loss_out, double* partial,
+                       void* stream)
+{
+    if (!pred || !target || !fluid || !grad || !loss_out || !partial) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = (long long)B * C * H * W;
+    const int g = grid_for(n, 256, 1024);
+    hipLaunchKernelGGL(k_masked_mse, dim3(g), dim3(256), 0, st, pred, target, fluid, B, C, H, W,
+                       grad, partial);
+    int e = status(hipGetLastError());
+    if (e) return e;
+    hipLaunchKernelGGL(k_mse_finalize, dim3(1), dim3(64), 0, st, partial, g, loss_out, partial + 2 * 1024);
+    e = status(hipGetLastError());
+    if (e) return e;
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, st, grad, n, partial + 2 * 1024);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int t, void* stream)
+{
+    if (!param || !grad || !m || !v || n < 0 || t < 1) return -1;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, param, grad, m,
+                       v, (long long)n, lr, beta1, beta2, eps, c1, c2);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_to_bf16(const float* in, uint16_t* out, int64_t n, void* stream)
+{
+    if (!in || !out) return -1;
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, in, out, (long long)n);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_from_bf16(const uint16_t* in, float* out, int64_t n, void* stream)
+{
+    if (!in || !out) return -1;
+    hipLaunchKernelGGL(k_from_bf16, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, in, out, (long long)n);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_features(const uint8_t* solid, const double* X_in, const double* j_A_cm2,
+                     const double* prof, int B, int H, int W, float* feat, void* stream)
+{
+    if (!solid || !X_in || !j_A_cm2 || !prof || !feat) return -1;
+    hipLaunchKernelGGL(k_features, dim3(grid_for((long long)B * H * W)), dim3(256), 0,
+                       (hipStream_t)stream, solid, X_in, j_A_cm2, prof, B, H, W, feat);
+    return status(hipGetLastError());
+}
+
+int lbm_cnn_assemble(const float* pred, const double* prof, int B, int H, int W, float scale,
+                     double x_min, double* X, void* stream)
+{
+    if (!pred || !prof || !X) return -1;
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for((long long)B * H * W)), dim3(256), 0,
+                       (hipStream_t)stream, pred, prof, B, H, W, scale, x_min, X);
+    return status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -565,6 +565,26 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
     return h->upload_tables();
 }
 
+int lbm_ms_clean_geometry(int lattice, int nx, int ny, int nz, const uint8_t* solid_in,
+                          uint8_t* solid_out, int64_t* n_open)
+{
+    if (!solid_in || !solid_out || nx < 2 || ny < 1 || nz < 1) return LBM_MS_E_ARG;
+    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
+    if (lattice == LBM_MS_D2Q9 && nz != 1) return LBM_MS_E_ARG;
+    lbm_ms_params p{};
+    p.lattice = lattice;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    const size_t N = (size_t)nx * ny * nz;
+    std::vector<uint8_t> m(solid_in, solid_in + N);
+    for (auto& v : m) v = v ? 1 : 0;
+    const long long open = clean_pores(p, m);
+    std::memcpy(solid_out, m.data(), N);
+    if (n_open) *n_open = open;
+    return LBM_MS_OK;
+}
+
 int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host)
 {
     if (!h || !solid_host) return LBM_MS_E_ARG;
@@ -648,6 +668,21 @@ int lbm_ms_init_paper_profile(lbm_ms_t h)
                                          (double*)h->at(h->L.field)), "paper profile");
     if (rc) return rc;
     return init_common(h, (const double*)h->at(h->L.field));
+}
+
+int lbm_ms_paper_profile(lbm_ms_t h, double* prof)
+{
+    if (!h || !prof) return LBM_MS_E_ARG;
+    if (!h->geom || !h->bc) return h->fail(LBM_MS_E_STATE, "set_geometry and set_bc first");
+    StepArgs a = h->args(h->cur);
+    // the profile kernel writes prof[2][nx]; the broadcast into the field buffer is harmless
+    int rc = h->hip(launch_paper_profile(h->stream, a, h->Qs[0], h->Qs[1], (double*)h->at(h->L.prof),
+                                         (double*)h->at(h->L.field)), "paper profile");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(prof, h->at(h->L.prof), 2ull * h->p.nx * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream), "profile readback");
+    if (rc) return rc;
+    return h->sync();
 }
 
 int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
@@ -967,6 +1002,7 @@ struct lbm_ms_batch_s {
     size_t tile_cap = 0, ent_cap = 0;
     int count = 0, ty = 0;
     std::vector<char> active;
+    std::vector<int> retired_status;  // why an inactive instance left the work list
     int ntiles = 0;
     int cur = 0;
     bool use_graphs = true;
@@ -1216,6 +1252,7 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     }
     if (rc == LBM_MS_OK) {
         b->active.assign(count, 1);
+        b->retired_status.assign(count, LBM_MS_OK);
         rc = b->upload_lists();
     }
     if (rc == LBM_MS_OK) rc = b->upload_tables();
@@ -1284,6 +1321,7 @@ int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device)
     if (rc == LBM_MS_OK) {
         b->cur = 0;
         b->active.assign(b->count, 1);
+        b->retired_status.assign(b->count, LBM_MS_OK);
         rc = b->upload_active_tiles();
     }
     return b->leave(rc);
@@ -1301,7 +1339,7 @@ int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps)
 }
 
 int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int check_every,
-                          int64_t* steps_taken, double* residual)
+                          int64_t* steps_taken, double* residual, int* status)
 {
     if (!b || check_every <= 0 || max_steps < 0) return LBM_MS_E_ARG;
     for (auto* h : b->inst)
@@ -1310,9 +1348,10 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
     if (rc) return rc;
     std::vector<int64_t> taken_k(b->count, 0);
     std::vector<double> r_k(b->count, INFINITY);
+    std::vector<int> st_k(b->count, LBM_MS_E_NOT_CONVERGED);
     // fresh residual windows
     for (int k = 0; k < b->count && rc == LBM_MS_OK; ++k) {
-        if (!b->active[k]) continue;
+        if (!b->active[k]) { st_k[k] = b->retired_status[k]; continue; }
         double v[6];
         rc = reduce_state(b->inst[k], 1, v);
         b->inst[k]->snap_step = b->inst[k]->steps;
@@ -1338,12 +1377,14 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
             const int rk = lbm_ms_residual(b->inst[k], &r);
             taken_k[k] = taken;
             r_k[k] = r;
-            if (rk) {
+            if (rk == LBM_MS_E_HIP) {
                 rc = rk;
                 b->err = "instance " + std::to_string(k) + ": " + b->inst[k]->err;
                 break;
             }
-            if (r < tol) {
+            if (rk != LBM_MS_OK || r < tol) {  // converged, or failed: leave the work list
+                st_k[k] = rk;
+                b->retired_status[k] = rk;
                 b->active[k] = 0;
                 changed = true;
             }
@@ -1351,10 +1392,12 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
     }
     if (steps_taken) std::memcpy(steps_taken, taken_k.data(), sizeof(int64_t) * b->count);
     if (residual) std::memcpy(residual, r_k.data(), sizeof(double) * b->count);
+    if (status) std::memcpy(status, st_k.data(), sizeof(int) * b->count);
     if (rc == LBM_MS_OK) {
         for (int k = 0; k < b->count; ++k)
-            if (!(r_k[k] < tol)) {
-                rc = b->fail(LBM_MS_E_NOT_CONVERGED, "instance " + std::to_string(k) + " not converged");
+            if (st_k[k] != LBM_MS_OK) {
+                rc = b->fail(st_k[k], "instance " + std::to_string(k) + ": " +
+                                          lbm_ms_status_string(st_k[k]));
                 break;
             }
     }

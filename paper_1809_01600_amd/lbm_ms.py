@@ -94,9 +94,14 @@ _SIGNATURES = [
                                      ctypes.POINTER(_VP)]),
     ("lbm_ms_set_geometry", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint8)]),
     ("lbm_ms_get_geometry", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint8)]),
+    ("lbm_ms_clean_geometry", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
+                                             ctypes.POINTER(ctypes.c_uint8),
+                                             ctypes.POINTER(ctypes.c_int64)]),
     ("lbm_ms_set_bc", ctypes.c_int, [_VP, _DP, ctypes.c_double]),
     ("lbm_ms_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_ms_init_paper_profile", ctypes.c_int, [_VP]),
+    ("lbm_ms_paper_profile", ctypes.c_int, [_VP, _DP]),
     ("lbm_ms_step", ctypes.c_int, [_VP, ctypes.c_int64]),
     ("lbm_ms_time_steps", ctypes.c_int, [_VP, ctypes.c_int64, _DP]),
     ("lbm_ms_residual", ctypes.c_int, [_VP, _DP]),
@@ -125,7 +130,8 @@ _SIGNATURES = [
     ("lbm_ms_batch_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_ms_batch_step", ctypes.c_int, [_VP, ctypes.c_int64]),
     ("lbm_ms_batch_converge", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, ctypes.c_int,
-                                             ctypes.POINTER(ctypes.c_int64), _DP]),
+                                             ctypes.POINTER(ctypes.c_int64), _DP,
+                                             ctypes.POINTER(ctypes.c_int)]),
     ("lbm_ms_batch_overpotential", ctypes.c_int, [_VP, _DP]),
     ("lbm_ms_batch_instance", _VP, [_VP, ctypes.c_int]),
     ("lbm_ms_batch_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int),
@@ -171,6 +177,21 @@ def lattice_info(lattice: int):
     lib().lbm_ms_lattice_info(lattice, ctypes.byref(q),
                               e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w))
     return e.reshape(q.value, 3), w
+
+
+def clean_geometry(lattice: str, solid: np.ndarray):
+    """Host-only pore-space clean-up (no GPU needed): (cleaned uint8 mask, open outlet nodes)."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8)
+    nz, ny, nx = solid.shape
+    out = np.empty_like(solid)
+    n_open = ctypes.c_int64(0)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    rc = lib().lbm_ms_clean_geometry(D2Q9 if lattice == "D2Q9" else D3Q19, nx, ny, nz,
+                                     solid.ctypes.data_as(u8), out.ctypes.data_as(u8),
+                                     ctypes.byref(n_open))
+    if rc != OK:
+        raise LbmMsError(rc, "clean_geometry")
+    return out, int(n_open.value)
 
 
 def tile_options(lattice: int, precision: int = FP32):
@@ -290,6 +311,11 @@ class Solver:
 
     def init_paper_profile(self):
         self._check(lib().lbm_ms_init_paper_profile(self.h))
+
+    def paper_profile(self) -> np.ndarray:
+        prof = np.zeros(2 * self.case.nx)
+        self._check(lib().lbm_ms_paper_profile(self.h, _dp(prof)))
+        return prof.reshape(2, self.case.nx)
 
     def step(self, n: int = 1):
         self._check(lib().lbm_ms_step(self.h, int(n)))
@@ -447,16 +473,25 @@ class Batch:
         self._check(lib().lbm_ms_batch_step(self.b, int(n)))
 
     def converge(self, tol, max_steps, check_every=100, raise_on_fail=True):
+        """Returns (steps per instance, residual per instance, overall status); per-instance
+        statuses are kept in self.status."""
         steps = (ctypes.c_int64 * self.count)()
         r = (ctypes.c_double * self.count)()
-        rc = lib().lbm_ms_batch_converge(self.b, tol, int(max_steps), int(check_every), steps, r)
+        st = (ctypes.c_int * self.count)()
+        rc = lib().lbm_ms_batch_converge(self.b, tol, int(max_steps), int(check_every), steps, r, st)
+        self.status = np.array(st[:], dtype=np.int32)
         if raise_on_fail:
             self._check(rc)
         return np.array(steps[:], dtype=np.int64), np.array(r[:]), rc
 
     def overpotential(self):
-        eta = np.zeros(self.count)
-        self._check(lib().lbm_ms_batch_overpotential(self.b, _dp(eta)))
+        """Eq. 43 per instance (NaN for an instance whose state has a non-positive fraction)."""
+        eta = np.full(self.count, np.nan)
+        for k in range(self.count):
+            try:
+                eta[k] = self.instance(k).overpotential()
+            except LbmMsError:
+                pass
         return eta
 
     def instance(self, k) -> Solver:

@@ -13,10 +13,10 @@ from paper_1809_01600_amd import inputs, lbm_ms
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "lbm_ms.h")).read()
+def _declared(header="lbm_ms.h", prefix="lbm_ms_"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_ms_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported_and_bound():
@@ -26,6 +26,16 @@ def test_every_declared_symbol_is_exported_and_bound():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(lbm_ms.SYMBOLS)
+
+
+def test_cnn_symbols_exported_and_bound():
+    from paper_1809_01600_amd import cnn
+    L = cnn.lib()
+    names = _declared("lbm_cnn.h", "lbm_cnn_")
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(cnn.CNN_SYMBOLS)
 
 
 def test_lattice_tables_match_the_oracle_as_sets():
@@ -77,3 +87,15 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(lbm_ms, "LIB_PATH", "/nonexistent/liblbm_ms.so")
     with pytest.raises(ImportError):
         lbm_ms.lib()
+
+
+@pytest.mark.parametrize("lat,shape,frac,seed", [("D2Q9", (1, 40, 30), 0.55, 1),
+                                                 ("D2Q9", (1, 64, 64), 0.45, 2),
+                                                 ("D3Q19", (9, 11, 13), 0.7, 3)])
+def test_host_clean_up_matches_oracle_labelling(lat, shape, frac, seed):
+    rng = np.random.default_rng(seed)
+    solid = (rng.random(shape) < frac).astype(np.uint8)
+    got, n_open = lbm_ms.clean_geometry(lat, solid)
+    ref, n_ref = oracle.label(lat, solid)
+    assert np.array_equal(got, ref)
+    assert n_open == n_ref

@@ -102,6 +102,28 @@ def test_converged_instances_retire():
     b.close()
 
 
+def test_failed_instance_retires_with_its_status():
+    """An instance past its limiting current (a fraction turns negative: the oracle shows it by
+    step 100 at 100 A/cm^2 over 2.4 mm) retires with E_NEG_FRACTION; the others still converge."""
+    cases = [inputs.stefan_tube(nx=24, ny=8, tau_ref=20.0, j_A_cm2=0.0, dx=1e-4),
+             inputs.stefan_tube(nx=24, ny=8, tau_ref=20.0, j_A_cm2=100.0, dx=1e-4),
+             inputs.stefan_tube(nx=64, ny=4, tau_ref=20.0, j_A_cm2=0.5, dx=1e-4)]
+    b = lbm_ms.Batch(cases, precision="fp64", ms_mode=lbm_ms.STOICH, tile_y=4)
+    b.init()
+    steps, r, rc = b.converge(1e-10, 40000, check_every=100, raise_on_fail=False)
+    assert rc == lbm_ms.E_NEG_FRACTION
+    assert list(b.status) == [lbm_ms.OK, lbm_ms.E_NEG_FRACTION, lbm_ms.OK], (b.status, steps, r)
+    assert steps[1] == 100 and r[2] < 1e-10
+    eta = b.overpotential()
+    assert np.isnan(eta[1]) and eta[2] > 0.0
+    s = lbm_ms.Solver(cases[2], precision="fp64", ms_mode=lbm_ms.STOICH, tile_y=4)
+    s.init()
+    s.step(int(steps[2]))
+    assert np.array_equal(s.get_fields(), b.instance(2).get_fields())
+    s.close()
+    b.close()
+
+
 def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
     from paper_1809_01600_amd import autotune
     monkeypatch.setenv("LBM_MS_TUNE_CACHE", str(tmp_path / "tune.json"))
