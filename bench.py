@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16"): 72,
                   ("D2Q9", "bf16"): 72, ("D3Q19", "fp64"): 608, ("D3Q19", "fp32"): 304,
                   ("D3Q19", "fp16"): 152, ("D3Q19", "bf16"): 152}
+NODE_SHIFT_BYTES = 2 * 8 * 2
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
                   "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
 
@@ -137,8 +138,8 @@ def main(argv=None):
     # step kernel alone: HIP events on the launch stream around K back-to-back launches
     kernel_ms = s.time_steps(K) / K
     bytes_per_launch = BYTES_PER_NODE[(case.lattice, args.precision)] * n_fluid
-    if shift == lbm_ms.SHIFT_NODE:
-        bytes_per_launch += 16 * n_fluid
+    if shift == lbm_ms.SHIFT_NODE:  # FP64 node reference per evolved species, read and written
+        bytes_per_launch += NODE_SHIFT_BYTES * n_fluid
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     wl_key = "%s_%s_%s" % (args.workload, args.precision, args.shift)
     traffic = measured_traffic(wl_key, kernel_hash())

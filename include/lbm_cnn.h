@@ -62,15 +62,22 @@ int lbm_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n,
 int lbm_cnn_to_bf16(const float* in, uint16_t* out, int64_t n, void* stream);
 int lbm_cnn_from_bf16(const uint16_t* in, float* out, int64_t n, void* stream);
 
-/* Input features [B][8][H][W]: fluid indicator, the inlet mole fractions X_in[B][3] broadcast,
- * j[B] (A/cm^2) / 2, x / (W - 1), and the paper's one-dimensional profile prof[B][2][W] (X_1,
- * X_2 along x) broadcast over y.  solid: [B][H][W] uint8. */
+/* Input features [B][8][H][W] and the baseline field the prediction corrects.  With phi(x) the
+ * fluid fraction of column x (at least 1/H) and prof[B][2][W] the paper's one-dimensional profile
+ * (X_1, X_2 along x), the porosity-weighted profile is P_s(x) = X_in,s + sum over x' <= x of
+ * (prof_s(x') - prof_s(x' - 1)) / phi(x'), with prof_s(-1) = X_in,s.  Channels: fluid indicator,
+ * X_in,1, X_in,2, j / 2 (j in A/cm^2), x / (W - 1), (P_1 - X_in,1) / 0.01, (P_2 - X_in,2) / 0.01,
+ * phi(x).  base[B][2][W] (float64) receives P.  solid: [B][H][W] uint8; X_in: [B][3];
+ * W <= 2048, B <= 65535. */
 int lbm_cnn_features(const uint8_t* solid, const double* X_in, const double* j_A_cm2,
-                     const double* prof, int B, int H, int W, float* feat, void* stream);
+                     const double* prof, int B, int H, int W, float* feat, double* base,
+                     void* stream);
 
-/* Initial field from a prediction pred[B][2][H][W]: X_s = prof_s + scale * pred_s (s = 1, 2),
- * each at least x_min, X_3 = 1 - X_1 - X_2 at least x_min (renormalized), written as
- * X[B][3][H][W] float64 (the layout lbm_ms_init / lbm_ms_batch_init take). */
+/* Initial field from a prediction pred[B][2][H][W] and a baseline prof[B][2][W] (the base output
+ * of lbm_cnn_features): X_s = max(prof_s + scale * pred_s, x_min)
+ * (s = 1, 2); where X_3 = 1 - X_1 - X_2 would fall below x_min, the parts of X_1 and X_2 above
+ * x_min are scaled so that X_3 = x_min.  Written as X[B][3][H][W] float64 (the layout
+ * lbm_ms_init / lbm_ms_batch_init take); 0 < x_min < 1/3. */
 int lbm_cnn_assemble(const float* pred, const double* prof, int B, int H, int W, float scale,
                      double x_min, double* X, void* stream);
 

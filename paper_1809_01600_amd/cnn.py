@@ -1,12 +1,15 @@
 """Warm-start network: five 3x3 convolution layers (8 -> 32 -> 32 -> 32 -> 32 -> 2 channels, ReLU
 between), trained and run with the hand-written HIP kernels of include/lbm_cnn.h.
 
-Inputs per pixel (8 channels): fluid indicator, inlet mole fractions X_in (3, broadcast), current
-density j / 2 A cm^-2, normalized x, and the paper's one-dimensional initial profile X_1, X_2
-along x (the field the paper starts from, Section 4.1).  The network predicts a correction on that
-profile: X_s = profile_s + SCALE * output_s (s = 1, 2), X_3 by closure, clipped to the simplex.
-The receptive field (11 x 11) only has to learn the pore-scale deviation; the profile carries the
-domain-scale trend.
+The paper starts its runs from a one-dimensional profile along x (Section 4.1): the flux equal to
+the electrode flux everywhere, in an open channel.  In a porous slice the same flux passes through
+a narrower and tortuous cross-section, so the steady depletion is several times larger.  The
+features carry a porosity-weighted version of that profile (its increments divided by the fluid
+fraction of each column), scaled to order one, together with the fluid indicator, X_in,1, X_in,2,
+j / 2 A cm^-2, normalized x and the column fluid fraction.  The network predicts the correction on
+the porosity-weighted profile: X_s = P_s + SCALE * output_s (s = 1, 2), X_3 by closure, kept on
+the simplex.  Its 11 x 11 receptive field learns the tortuosity factor and the pore-scale
+deviation; the profile carries the domain-scale trend.
 
 Argument marshalling only: the arithmetic runs in the library's kernels, on the current torch
 stream.
@@ -40,7 +43,7 @@ _CNN_SIGNATURES = [
                           ctypes.c_float, ctypes.c_float, _I, _VP]),
     ("lbm_cnn_to_bf16", _I, [_VP, _VP, ctypes.c_int64, _VP]),
     ("lbm_cnn_from_bf16", _I, [_VP, _VP, ctypes.c_int64, _VP]),
-    ("lbm_cnn_features", _I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP, _VP]),
+    ("lbm_cnn_features", _I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP, _VP, _VP]),
     ("lbm_cnn_assemble", _I, [_VP, _VP, _I, _I, _I, ctypes.c_float, ctypes.c_double, _VP, _VP]),
 ]
 CNN_SYMBOLS = [s[0] for s in _CNN_SIGNATURES]
@@ -198,26 +201,27 @@ class WarmStartNet:
 
 def features(solid, X_in, j_A_cm2, prof):
     """Device tensors: solid uint8 [B,H,W], X_in f64 [B,3], j f64 [B], prof f64 [B,2,W] ->
-    features f32 [B,8,H,W]."""
+    (features f32 [B,8,H,W], baseline f64 [B,2,W]: the porosity-weighted profile)."""
     import torch
     B, H, W = solid.shape
     feat = torch.empty((B, CIN, H, W), dtype=torch.float32, device=solid.device)
+    base = torch.empty((B, 2, W), dtype=torch.float64, device=solid.device)
     _ok(lib().lbm_cnn_features(_p(solid.contiguous()), _p(X_in.contiguous()), _p(j_A_cm2.contiguous()),
-                               _p(prof.contiguous()), B, H, W, _p(feat), _stream()), "features")
-    return feat
+                               _p(prof.contiguous()), B, H, W, _p(feat), _p(base), _stream()),
+        "features")
+    return feat, base
 
 
-def assemble(pred, prof, x_min=1e-6):
-    """Prediction [B,2,H,W] + profile [B,2,W] -> initial field [B,3,H,W] float64 on the device."""
+def assemble(pred, base, x_min=1e-6):
+    """Prediction [B,2,H,W] + baseline [B,2,W] -> initial field [B,3,H,W] float64 on the device."""
     import torch
     B, _, H, W = pred.shape
     X = torch.empty((B, 3, H, W), dtype=torch.float64, device=pred.device)
-    _ok(lib().lbm_cnn_assemble(_p(pred.contiguous()), _p(prof.contiguous()), B, H, W, SCALE, x_min,
+    _ok(lib().lbm_cnn_assemble(_p(pred.contiguous()), _p(base.contiguous()), B, H, W, SCALE, x_min,
                                _p(X), _stream()), "assemble")
     return X
 
 
-def targets(X, prof):
-    """Training targets (X_s - profile_s) / SCALE for s = 1, 2 (torch, device)."""
-    W = X.shape[-1]
-    return ((X[:, :2] - prof[:, :, None, :]) / SCALE).float().contiguous()
+def targets(X, base):
+    """Training targets (X_s - base_s) / SCALE for s = 1, 2 (torch, device)."""
+    return ((X[:, :2] - base[:, :, None, :]) / SCALE).float().contiguous()

@@ -268,25 +268,64 @@ __global__ void k_from_bf16(const uint16_t* __restrict__ in, float* __restrict__
         out[i] = bf16_to_f32(in[i]);
 }
 
-__global__ void k_features(const uint8_t* __restrict__ solid, const double* __restrict__ X_in,
-                           const double* __restrict__ j, const double* __restrict__ prof, int B,
-                           int H, int W, float* __restrict__ feat)
+// Feature rows [y0, y0 + FEAT_ROWS) of instance blockIdx.y.  Every workgroup first rebuilds the
+// per-column fluid fraction phi(x) and the porosity-weighted profile in LDS (a column scan per
+// species), then writes its rows of the eight channels; the first row block also writes the
+// profile itself (the baseline the prediction corrects).
+constexpr int FEAT_ROWS = 16;
+constexpr int FEAT_MAX_W = 2048;  // LDS: 4 W + 16 W bytes
+constexpr float DEPLETION_SCALE = 0.01f;
+
+__global__ void __launch_bounds__(256) k_features(const uint8_t* __restrict__ solid,
+                                                  const double* __restrict__ X_in,
+                                                  const double* __restrict__ j,
+                                                  const double* __restrict__ prof, int H, int W,
+                                                  float* __restrict__ feat,
+                                                  double* __restrict__ base)
 {
+    extern __shared__ int lds[];
+    int* cnt = lds;                                                   // [W] fluid per column
+    double* pp = reinterpret_cast<double*>(lds + 2 * ((W + 1) / 2));  // [2][W], 8-byte aligned
+    const int b = blockIdx.y;
     const long long plane = (long long)H * W;
-    const long long n = (long long)B * plane;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long b = i / plane, p = i % plane;
-        const int x = (int)(p % W);
-        float* f = feat + b * 8 * plane + p;
-        f[0] = solid[i] ? 0.f : 1.f;
-        f[plane] = (float)X_in[3 * b];
-        f[2 * plane] = (float)X_in[3 * b + 1];
-        f[3 * plane] = (float)X_in[3 * b + 2];
-        f[4 * plane] = (float)(0.5 * j[b]);
-        f[5 * plane] = W > 1 ? (float)x / (float)(W - 1) : 0.f;
-        f[6 * plane] = (float)prof[(b * 2) * W + x];
-        f[7 * plane] = (float)prof[(b * 2 + 1) * W + x];
+    const uint8_t* sb = solid + b * plane;
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+        int c = 0;
+        for (int y = 0; y < H; ++y) c += sb[(long long)y * W + x] ? 0 : 1;
+        cnt[x] = c > 0 ? c : 1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int sp = threadIdx.x;
+        const double* pr = prof + (long long)(b * 2 + sp) * W;
+        double prev = X_in[3 * b + sp], acc = prev;
+        for (int x = 0; x < W; ++x) {
+            const double v = pr[x];
+            acc += (v - prev) * (double)H / (double)cnt[x];
+            prev = v;
+            pp[sp * W + x] = acc;
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < 2 * W; i += blockDim.x) base[(long long)b * 2 * W + i] = pp[i];
+    const int y0 = blockIdx.x * FEAT_ROWS;
+    const int rows = min(FEAT_ROWS, H - y0);
+    float* fb = feat + b * 8 * plane;
+    const double x1 = X_in[3 * b], x2 = X_in[3 * b + 1];
+    const float jj = (float)(0.5 * j[b]);
+    const float rw = W > 1 ? 1.f / (float)(W - 1) : 0.f;
+    for (int i = threadIdx.x; i < rows * W; i += blockDim.x) {
+        const int x = i % W;
+        const long long p = (long long)(y0 + i / W) * W + x;
+        fb[p] = sb[p] ? 0.f : 1.f;
+        fb[plane + p] = (float)x1;
+        fb[2 * plane + p] = (float)x2;
+        fb[3 * plane + p] = jj;
+        fb[4 * plane + p] = (float)x * rw;
+        fb[5 * plane + p] = (float)(pp[x] - x1) / DEPLETION_SCALE;
+        fb[6 * plane + p] = (float)(pp[W + x] - x2) / DEPLETION_SCALE;
+        fb[7 * plane + p] = (float)cnt[x] / (float)H;
     }
 }
 
@@ -304,10 +343,10 @@ __global__ void k_assemble(const float* __restrict__ pred, const double* __restr
         x1 = x1 > x_min ? x1 : x_min;
         x2 = x2 > x_min ? x2 : x_min;
         double x3 = 1.0 - x1 - x2;
-        if (x3 < x_min) {
-            const double s = (1.0 - x_min) / (x1 + x2);
-            x1 *= s;
-            x2 *= s;
+        if (x3 < x_min) {  // take the excess from the parts of X_1, X_2 above x_min
+            const double s = (1.0 - 3.0 * x_min) / (x1 + x2 - 2.0 * x_min);
+            x1 = x_min + (x1 - x_min) * s;
+            x2 = x_min + (x2 - x_min) * s;
             x3 = 1.0 - x1 - x2;
         }
         X[(b * 3) * plane + p] = x1;
@@ -454,18 +493,24 @@ int lbm_cnn_from_bf16(const uint16_t* in, float* out, int64_t n, void* stream)
 }
 
 int lbm_cnn_features(const uint8_t* solid, const double* X_in, const double* j_A_cm2,
-                     const double* prof, int B, int H, int W, float* feat, void* stream)
+                     const double* prof, int B, int H, int W, float* feat, double* base,
+                     void* stream)
 {
-    if (!solid || !X_in || !j_A_cm2 || !prof || !feat) return -1;
-    hipLaunchKernelGGL(k_features, dim3(grid_for((long long)B * H * W)), dim3(256), 0,
-                       (hipStream_t)stream, solid, X_in, j_A_cm2, prof, B, H, W, feat);
+    if (!solid || !X_in || !j_A_cm2 || !prof || !feat || !base || B <= 0 || H <= 0 || W <= 0 ||
+        W > FEAT_MAX_W || B > 65535)
+        return -1;
+    const dim3 grid((H + FEAT_ROWS - 1) / FEAT_ROWS, B);
+    const size_t lds = 2 * ((W + 1) / 2) * sizeof(int) + 2 * W * sizeof(double);
+    hipLaunchKernelGGL(k_features, grid, dim3(256), lds, (hipStream_t)stream, solid, X_in,
+                       j_A_cm2, prof, H, W, feat, base);
     return status(hipGetLastError());
 }
 
 int lbm_cnn_assemble(const float* pred, const double* prof, int B, int H, int W, float scale,
                      double x_min, double* X, void* stream)
 {
-    if (!pred || !prof || !X) return -1;
+    if (!pred || !prof || !X || B <= 0 || H <= 0 || W <= 0 || !(x_min > 0.0 && x_min < 1.0 / 3.0))
+        return -1;
     hipLaunchKernelGGL(k_assemble, dim3(grid_for((long long)B * H * W)), dim3(256), 0,
                        (hipStream_t)stream, pred, prof, B, H, W, scale, x_min, X);
     return status(hipGetLastError());

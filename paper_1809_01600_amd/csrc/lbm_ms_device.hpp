@@ -110,8 +110,8 @@ __device__ inline void gstore(void* base, unsigned byte_off, T v)
 struct StepArgs {
     const void* fin;          // post-collision populations of step t   [2][Q][P] (fluid nodes)
     void* fout;               // post-collision populations of step t+1 [2][Q][P]
-    const float* xin;         // node shift field of step t   [2][NF] (NODE shift only)
-    float* xout;              // node shift field of step t+1 [2][NF]
+    const double* xin;        // node reference c of step t   [2][NF] (NODE shift only)
+    double* xout;             // node reference c of step t+1 [2][NF]
     const int* idx;           // dense [N]: compact fluid index of the node, -1 for solid
     unsigned* flags;          // [0]: relaxation time clamped
     long long N;              // nodes of the box
@@ -195,11 +195,106 @@ __device__ inline uint32_t global_sources(const StepArgs& a, int x, int y, int z
 
 // Branch-free gather of the post-stream populations of compact node i from its source slots,
 // then the inlet rule and the moments.  A lane with nothing to do passes i = 0 and zero slots.
+//
+// NODE shift: a stored post-collision population is f*_a = w_a c + h_a, with c an FP64 reference
+// per node and species and h_a in the storage precision.  The slowest mode of a steady solve
+// lives in the moment X, so X is carried in FP64 and only the small deviations h_a are rounded:
+// for the links of node i, dc_a = c(source) - c(i) and h_a are small, X = c(i) + sum_a (w_a dc_a
+// + h_a), and the output is g_a = f_a - w_a X = w_a (dc_a - S) + h_a with S = X - c(i).
+// Where the references c come from: global memory by compact index, or an LDS-staged copy of the
+// region around the node (position pos, row pitch RX).
+struct RefGlobal {
+    const double* xin;
+    unsigned xsp;  // bytes per species
+    __device__ inline double own(int s, int i) const { return gload<double>(xin, (unsigned)i * 8u + s * xsp); }
+    template <class L>
+    __device__ inline double src(int s, int k, unsigned m) const { return gload<double>(xin, m * 8u + s * xsp); }
+};
+template <int RX, int RY>
+struct RefLds {
+    const double* sc;  // [2][RY * RX]
+    int pos;
+    __device__ inline double own(int s, int) const { return sc[s * RY * RX + pos]; }
+    template <class L>
+    __device__ inline double src(int s, int k, unsigned) const
+    {
+        return sc[s * RY * RX + pos - L::ey[k] * RX - L::ex[k]];
+    }
+};
+
+template <class L, int P, class REF>
+__device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                                 bool outlet, float (&g)[2][L::Q], double& X0, double& X1,
+                                 const REF& ref)
+{
+    using C = Codec<P>;
+    using raw = typename C::raw;
+    constexpr unsigned ES = sizeof(raw);
+    const void* fin = a.fin;
+    const unsigned plane = (unsigned)a.P * ES;
+    const unsigned spec = (unsigned)L::Q * plane;
+    const double co0 = ref.own(0, i);
+    const double co1 = ref.own(1, i);
+    const bool wall = a.inlet_wall != 0;
+    float dc[2][L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const int ex = L::ex[k];
+        const bool from_out = (ex == -1) && outlet;
+        const bool from_in = (ex == 1) && inlet;
+        const int s = si[k];
+        const bool local = (s < 0) || from_out || from_in;
+        const bool reflect = (s == -1) || from_out || (from_in && wall);
+        const unsigned m = (unsigned)(local ? i : s);
+        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + m * ES;
+        g[0][k] = C::dec(gload<raw>(fin, off), 0.f);
+        g[1][k] = C::dec(gload<raw>(fin, off + spec), 0.f);
+        dc[0][k] = local ? 0.f : (float)(ref.template src<L>(0, k, m) - co0);
+        dc[1][k] = local ? 0.f : (float)(ref.template src<L>(1, k, m) - co1);
+        if (L::ex[k] == -1) {
+            const float frac = (float)(L::w[L::opp[k]] / W_OUT);
+            g[0][k] = from_out ? g[0][k] - frac * (float)a.Q0 : g[0][k];
+            g[1][k] = from_out ? g[1][k] - frac * (float)a.Q1 : g[1][k];
+        }
+    }
+    // Eq. 36: f_a = 2 w_a X_in - f_abar, i.e. reference 2 X_in - c_abar and deviation -h_abar
+    const bool anti = inlet && !wall;
+    const float di0 = (float)(2.0 * (a.Xin0 - co0)), di1 = (float)(2.0 * (a.Xin1 - co1));
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        if (L::ex[k] == 1) {
+            const int o = L::opp[k];
+            dc[0][k] = anti ? di0 - dc[0][o] : dc[0][k];
+            dc[1][k] = anti ? di1 - dc[1][o] : dc[1][k];
+            g[0][k] = anti ? -g[0][o] : g[0][k];
+            g[1][k] = anti ? -g[1][o] : g[1][k];
+        }
+    }
+    double S0 = 0.0, S1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        S0 += (double)((float)L::w[k] * dc[0][k]) + (double)g[0][k];
+        S1 += (double)((float)L::w[k] * dc[1][k]) + (double)g[1][k];
+    }
+    X0 = co0 + S0;
+    X1 = co1 + S1;
+    const float s0 = (float)S0, s1 = (float)S1;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        g[0][k] += (float)L::w[k] * (dc[0][k] - s0);
+        g[1][k] += (float)L::w[k] * (dc[1][k] - s1);
+    }
+}
+
 template <class L, int P, bool NS>
 __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
                               bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
                               double& X1)
 {
+    if constexpr (NS) {
+        gather_ns<L, P>(a, i, si, inlet, outlet, f, X0, X1, RefGlobal{a.xin, (unsigned)a.NF * 8u});
+        return;
+    }
     using C = Codec<P>;
     using CT = typename C::CT;
     using raw = typename C::raw;
@@ -207,12 +302,6 @@ __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], b
     const void* fin = a.fin;
     const unsigned plane = (unsigned)a.P * ES;          // bytes per (species, link) plane
     const unsigned spec = (unsigned)L::Q * plane;       // bytes per species
-    const unsigned xsp = (unsigned)a.NF * 4u;           // bytes per species of the shift field
-    float sh_own0 = 0.f, sh_own1 = 0.f;
-    if constexpr (NS) {
-        sh_own0 = gload<float>(a.xin, (unsigned)i * 4u);
-        sh_own1 = gload<float>(a.xin, (unsigned)i * 4u + xsp);
-    }
     const float cg0 = (float)a.c0, cg1 = (float)a.c1;
     const bool wall = a.inlet_wall != 0;
 #pragma unroll
@@ -229,16 +318,8 @@ __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], b
         const raw r1 = gload<raw>(fin, off + spec);
         if constexpr (C::shifted) {
             const float wk = (float)L::w[k];  // w of the opposite link is the same
-            float s0, s1;
-            if constexpr (NS) {
-                s0 = wk * (local ? sh_own0 : gload<float>(a.xin, m * 4u));
-                s1 = wk * (local ? sh_own1 : gload<float>(a.xin, m * 4u + xsp));
-            } else {
-                s0 = wk * cg0;
-                s1 = wk * cg1;
-            }
-            f[0][k] = C::dec(r0, s0);
-            f[1][k] = C::dec(r1, s1);
+            f[0][k] = C::dec(r0, wk * cg0);
+            f[1][k] = C::dec(r1, wk * cg1);
         } else {
             f[0][k] = C::dec(r0, CT(0));
             f[1][k] = C::dec(r1, CT(0));
@@ -349,6 +430,9 @@ __device__ inline double grad1(bool up, bool dn, double xu, double xc, double xd
 }
 
 // BGK collision toward w_a X_s (Eq. 28-29) and store of the post-collision populations.
+// NODE shift: f holds g_a = f_a - w_a X, so f*_a = w_a X + (1 - omega) g_a; the deviations are
+// rounded to the storage precision and the node reference c = X - sum_a h_a (FP64) keeps the
+// stored moment equal to X whatever the rounding.
 template <class L, int P, bool NS>
 __device__ inline void collide_store(const StepArgs& a, int n,
                                      typename Codec<P>::CT (&f)[2][L::Q], double X0, double X1,
@@ -362,15 +446,26 @@ __device__ inline void collide_store(const StepArgs& a, int n,
     const unsigned plane = (unsigned)a.P * ES;
     const unsigned spec = (unsigned)L::Q * plane;
     const unsigned base = (unsigned)n * ES;
+    if constexpr (NS) {
+        const float k0 = (float)(1.0 - om0), k1 = (float)(1.0 - om1);
+        double sh0 = 0.0, sh1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < L::Q; ++k) {
+            const raw r0 = C::enc(k0 * f[0][k], 0.f);
+            const raw r1 = C::enc(k1 * f[1][k], 0.f);
+            sh0 += (double)C::dec(r0, 0.f);
+            sh1 += (double)C::dec(r1, 0.f);
+            const unsigned off = base + (unsigned)k * plane;
+            gstore<raw>(fout, off, r0);
+            gstore<raw>(fout, off + spec, r1);
+        }
+        gstore<double>(a.xout, (unsigned)n * 8u, X0 - sh0);
+        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 - sh1);
+        return;
+    }
     const CT o0 = (CT)om0, o1 = (CT)om1;
     const CT x0 = (CT)X0, x1 = (CT)X1;
-    float c0 = (float)a.c0, c1 = (float)a.c1;
-    if constexpr (NS) {
-        c0 = (float)X0;
-        c1 = (float)X1;
-        gstore<float>(a.xout, (unsigned)n * 4u, c0);
-        gstore<float>(a.xout, (unsigned)n * 4u + (unsigned)a.NF * 4u, c1);
-    }
+    const float c0 = (float)a.c0, c1 = (float)a.c1;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const CT wk = (CT)L::w[k];

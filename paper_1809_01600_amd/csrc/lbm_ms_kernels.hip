@@ -66,6 +66,35 @@ __device__ inline void stage_plane(const StepArgs& a, int x0, int y0, int z, int
     }
 }
 
+// stage_plane plus, for the NODE shift, the FP64 references c of every staged fluid node
+// (loaded by the same thread right after its index, so one barrier covers both).
+template <int RX, int RY>
+__device__ inline void stage_plane_refs(const StepArgs& a, int x0, int y0, int* dst, double* sc)
+{
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int rx = t % RX, ry = t / RX;
+        const int gx = x0 - 2 + rx;
+        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int i = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)((long long)gy * a.nx + gx) * 4u) : -2;
+        dst[t] = i;
+        sc[t] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
+        sc[RX * RY + t] = i >= 0 ? gload<double>(a.xin, (unsigned)(a.NF + i) * 8u) : 0.0;
+    }
+}
+
+// Pull of one node of a 2D tile: NODE-shift references from the staged region, else the plain
+// gather.  (cx, cy): the node's position in the staged region.
+template <int P, bool NS, int RX, int RY>
+__device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[D2Q9::Q], bool inlet,
+                                bool outlet, typename Codec<P>::CT (&f)[2][D2Q9::Q], double& X0,
+                                double& X1, const double* sc, int cx, int cy)
+{
+    if constexpr (NS)
+        gather_ns<D2Q9, P>(a, i, si, inlet, outlet, f, X0, X1, RefLds<RX, RY>{sc, cy * RX + cx});
+    else
+        gather<D2Q9, P, false>(a, i, si, inlet, outlet, f, X0, X1);
+}
+
 // ---------------------------------------------------------------------------------------------
 // 2D (D2Q9): a work list of 64 x TY tiles.  Each tile record names its instance (one problem of
 // a batch), its origin, and two entry lists built on the host: the tile's fluid nodes and the
@@ -85,6 +114,7 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
     constexpr int TX = 64, RX = TX + 4, RY = TY + 4, BS = 32 * TY;
     __shared__ int sI[RY * RX];
     __shared__ double sX[2][TY + 2][TX + 2];
+    __shared__ double sC[NS ? 2 * RY * RX : 1];  // NODE shift: staged references
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const unsigned tb = (unsigned)tile * 32u;
@@ -101,7 +131,10 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
     pe[0] = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
     pe[1] = two && threadIdx.x + BS < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x + BS) * 4u) : dummy;
     pe[2] = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
-    stage_plane<RX, RY>(a, x0, y0, 0, sI);
+    if constexpr (NS)
+        stage_plane_refs<RX, RY>(a, x0, y0, sI, sC);
+    else
+        stage_plane<RX, RY>(a, x0, y0, 0, sI);
     __syncthreads();
 
     // own nodes (entries t and t + BS) and the first halo entry: all loads issued together
@@ -119,8 +152,9 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
         const int x = x0 + cxo[u] - 1;
         int si[L::Q];
         nbo[u] = lds_sources<L, RX, RY, 1>(sI, -2, cxo[u] + 1, cyo[u] + 1, x, a.nx, io[u], si);
-        gather<L, P, NS>(a, io[u] < 0 ? 0 : io[u], si, io[u] >= 0 && x == 0,
-                         io[u] >= 0 && x == a.nx - 1, f[u], X0[u], X1[u]);
+        gather2d<P, NS, RX, RY>(a, io[u] < 0 ? 0 : io[u], si, io[u] >= 0 && x == 0,
+                                io[u] >= 0 && x == a.nx - 1, f[u], X0[u], X1[u], sC, cxo[u] + 1,
+                                cyo[u] + 1);
     }
     if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
         const int cx = pe[2] & 255u, cy = pe[2] >> 8;
@@ -131,7 +165,8 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
         lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
         CT hf[2][L::Q];
         double h0, h1;
-        gather<L, P, NS>(a, hi < 0 ? 0 : hi, si, hi >= 0 && x == 0, hi >= 0 && x == a.nx - 1, hf, h0, h1);
+        gather2d<P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && x == 0, hi >= 0 && x == a.nx - 1,
+                                hf, h0, h1, sC, cx + 1, cy + 1);
         if (job) {
             sX[0][cy][cx] = h0;
             sX[1][cy][cx] = h1;
@@ -147,7 +182,7 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
         lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
         CT hf[2][L::Q];
         double h0, h1;
-        gather<L, P, NS>(a, hi, si, x == 0, x == a.nx - 1, hf, h0, h1);
+        gather2d<P, NS, RX, RY>(a, hi, si, x == 0, x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
         sX[0][cy][cx] = h0;
         sX[1][cy][cx] = h1;
     }
@@ -334,12 +369,16 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
         if (i < 0) continue;
         const double v0 = X ? X[n] : u0;
         const double v1 = X ? X[N + n] : u1;
-        float c0 = (float)a.c0, c1 = (float)a.c1;
-        if constexpr (NS) {
-            c0 = (float)v0;
-            c1 = (float)v1;
-            a.xout[i] = c0;
-            a.xout[a.NF + i] = c1;
+        const float c0 = (float)a.c0, c1 = (float)a.c1;
+        if constexpr (NS) {  // reference c = X, deviations zero
+            a.xout[i] = v0;
+            a.xout[a.NF + i] = v1;
+#pragma unroll
+            for (int k = 0; k < L::Q; ++k) {
+                fout[(long long)k * a.P + i] = C::enc(0.f, 0.f);
+                fout[(long long)(L::Q + k) * a.P + i] = C::enc(0.f, 0.f);
+            }
+            continue;
         }
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
@@ -363,15 +402,18 @@ __device__ inline void node_moments(const StepArgs& a, int i, double& X0, double
     using C = Codec<P>;
     using raw = typename C::raw;
     const raw* fin = static_cast<const raw*>(a.fin);
-    float c0 = (float)a.c0, c1 = (float)a.c1;
-    if constexpr (NS) {
-        c0 = a.xin[i];
-        c1 = a.xin[a.NF + i];
-    }
+    const float c0 = (float)a.c0, c1 = (float)a.c1;
     double s0 = 0.0, s1 = 0.0;
+    if constexpr (NS) {  // X = c + sum_a h_a
+        s0 = a.xin[i];
+        s1 = a.xin[a.NF + i];
+    }
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        if constexpr (C::shifted) {
+        if constexpr (NS) {
+            s0 += (double)C::dec(fin[(long long)k * a.P + i], 0.f);
+            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], 0.f);
+        } else if constexpr (C::shifted) {
             const float wf = (float)L::w[k];
             s0 += (double)C::dec(fin[(long long)k * a.P + i], wf * c0);
             s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], wf * c1);
@@ -473,18 +515,24 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
             CT f[2][L::Q];
             double X0, X1;
             pull_node<L, P, NS>(a, x, y, z, n, i, f, X0, X1);
-            float c0 = (float)a.c0, c1 = (float)a.c1;
-            if constexpr (NS) {
-                c0 = a.xin[i];
-                c1 = a.xin[a.NF + i];
-            }
+            const float c0 = (float)a.c0, c1 = (float)a.c1;
             double cross0 = 0.0, cross1 = 0.0;  // net +x transfer across the face
 #pragma unroll
             for (int q = 0; q < L::Q; ++q) {
                 if (L::ex[q] == 0) continue;
+                // post-stream population (NODE shift: f = w X + g)
+                double p0 = (double)f[0][q], p1 = (double)f[1][q];
+                if constexpr (NS) {
+                    p0 += L::w[q] * X0;
+                    p1 += L::w[q] * X1;
+                }
                 // post-collision population of this node leaving through the face
                 double o0, o1;
-                if constexpr (C::shifted) {
+                if constexpr (NS) {
+                    o0 = L::w[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
+                    o1 = L::w[q] * a.xin[a.NF + i] +
+                         (double)C::dec(fin[(long long)(L::Q + q) * a.P + i], 0.f);
+                } else if constexpr (C::shifted) {
                     const float wf = (float)L::w[q];
                     o0 = C::dec(fin[(long long)q * a.P + i], wf * c0);
                     o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], wf * c1);
@@ -493,11 +541,11 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                     o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], 0);
                 }
                 if (side == 0) {
-                    if (L::ex[q] == 1) { cross0 += (double)f[0][q]; cross1 += (double)f[1][q]; }
+                    if (L::ex[q] == 1) { cross0 += p0; cross1 += p1; }
                     else { cross0 -= o0; cross1 -= o1; }
                 } else {
                     if (L::ex[q] == 1) { cross0 += o0; cross1 += o1; }
-                    else { cross0 -= (double)f[0][q]; cross1 -= (double)f[1][q]; }
+                    else { cross0 -= p0; cross1 -= p1; }
                 }
             }
             if (side == 0) {
@@ -549,10 +597,10 @@ __global__ void k_populations(StepArgs a, int s, int q, double* out)
         double v = 0.0;
         const int i = a.idx[n];
         if (i >= 0) {
-            float c = (float)(s ? a.c1 : a.c0);
-            if constexpr (NS) c = a.xin[(long long)s * a.NF + i];
+            const float c = (float)(s ? a.c1 : a.c0);
             const raw r = fin[((long long)s * L::Q + q) * a.P + i];
-            if constexpr (C::shifted) v = C::dec(r, (float)L::w[q] * c);
+            if constexpr (NS) v = L::w[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
+            else if constexpr (C::shifted) v = C::dec(r, (float)L::w[q] * c);
             else v = C::dec(r, 0);
         }
         out[n] = v;
@@ -677,7 +725,8 @@ hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tile
 {
     switch (prec) {
     case P_F64: return launch_step2d_p<P_F64, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_F32: return launch_step2d_p<P_F32, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F32: return node_shift ? launch_step2d_p<P_F32, true>(st, insts, tiles, ent, ntiles, ty)
+                                  : launch_step2d_p<P_F32, false>(st, insts, tiles, ent, ntiles, ty);
     case P_F16: return node_shift ? launch_step2d_p<P_F16, true>(st, insts, tiles, ent, ntiles, ty)
                                   : launch_step2d_p<P_F16, false>(st, insts, tiles, ent, ntiles, ty);
     case P_BF16: return node_shift ? launch_step2d_p<P_BF16, true>(st, insts, tiles, ent, ntiles, ty)
@@ -703,7 +752,8 @@ hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec,
 {
     switch (prec) {
     case P_F64: return launch_step_p<P_F64, false>(st, a, lattice, ty, cz, nblocks);
-    case P_F32: return launch_step_p<P_F32, false>(st, a, lattice, ty, cz, nblocks);
+    case P_F32: return node_shift ? launch_step_p<P_F32, true>(st, a, lattice, ty, cz, nblocks)
+                                  : launch_step_p<P_F32, false>(st, a, lattice, ty, cz, nblocks);
     case P_F16: return node_shift ? launch_step_p<P_F16, true>(st, a, lattice, ty, cz, nblocks)
                                   : launch_step_p<P_F16, false>(st, a, lattice, ty, cz, nblocks);
     case P_BF16: return node_shift ? launch_step_p<P_BF16, true>(st, a, lattice, ty, cz, nblocks)
@@ -718,7 +768,7 @@ static hipError_t dispatch(int lattice, int prec, int ns, Args&&... args)
 #define LBMMS_CASES(LAT)                                                                   \
     switch (prec) {                                                                        \
     case P_F64: return Fn<LAT, P_F64, false>::run(args...);                                \
-    case P_F32: return Fn<LAT, P_F32, false>::run(args...);                                \
+    case P_F32: return ns ? Fn<LAT, P_F32, true>::run(args...) : Fn<LAT, P_F32, false>::run(args...); \
     case P_F16: return ns ? Fn<LAT, P_F16, true>::run(args...) : Fn<LAT, P_F16, false>::run(args...); \
     case P_BF16: return ns ? Fn<LAT, P_BF16, true>::run(args...) : Fn<LAT, P_BF16, false>::run(args...); \
     }

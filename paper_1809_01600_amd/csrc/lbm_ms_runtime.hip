@@ -43,8 +43,7 @@ size_t elem_bytes(int prec)
 
 bool node_shift(const lbm_ms_params& p)
 {
-    return (p.precision == LBM_MS_FP16 || p.precision == LBM_MS_BF16) &&
-           p.shift_mode == LBM_MS_SHIFT_NODE;
+    return p.precision != LBM_MS_FP64 && p.shift_mode == LBM_MS_SHIFT_NODE;
 }
 
 bool valid_params(const lbm_ms_params* p, std::string* why)
@@ -92,7 +91,7 @@ Layout layout(const lbm_ms_params& p)
     const size_t fb = 2ull * q * (size_t)plane_pitch((long long)N) * elem_bytes(p.precision);
     L.f[0] = take(fb);
     L.f[1] = take(fb);
-    const size_t xb = node_shift(p) ? 2ull * N * sizeof(float) : 0;
+    const size_t xb = node_shift(p) ? 2ull * N * sizeof(double) : 0;
     L.xn[0] = take(xb);
     L.xn[1] = take(xb);
     L.idx = take(N * sizeof(int32_t));
@@ -167,8 +166,8 @@ struct lbm_ms_s {
         StepArgs a{};
         a.fin = ws + L.f[in_buf];
         a.fout = ws + L.f[1 - in_buf];
-        a.xin = node_shift(p) ? reinterpret_cast<const float*>(ws + L.xn[in_buf]) : nullptr;
-        a.xout = node_shift(p) ? reinterpret_cast<float*>(ws + L.xn[1 - in_buf]) : nullptr;
+        a.xin = node_shift(p) ? reinterpret_cast<const double*>(ws + L.xn[in_buf]) : nullptr;
+        a.xout = node_shift(p) ? reinterpret_cast<double*>(ws + L.xn[1 - in_buf]) : nullptr;
         a.idx = reinterpret_cast<const int*>(ws + L.idx);
         a.flags = reinterpret_cast<unsigned*>(ws + L.flags);
         a.N = N;
@@ -905,7 +904,7 @@ int lbm_ms_save_state(lbm_ms_t h, void* buf, size_t* bytes)
 {
     if (!h || !bytes) return LBM_MS_E_ARG;
     const size_t fb = 2ull * h->q * h->P * elem_bytes(h->p.precision);
-    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(float) : 0;
+    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(double) : 0;
     const size_t sb = 2ull * h->n_fluid * sizeof(double);
     const size_t need = sizeof(StateHeader) + fb + xb + sb;
     if (!buf) { *bytes = need; return LBM_MS_OK; }
@@ -937,7 +936,7 @@ int lbm_ms_load_state(lbm_ms_t h, const void* buf, size_t bytes)
     if (bytes < sizeof(H)) return h->fail(LBM_MS_E_ARG, "blob too small");
     std::memcpy(&H, buf, sizeof(H));
     const size_t fb = 2ull * h->q * h->P * elem_bytes(h->p.precision);
-    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(float) : 0;
+    const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(double) : 0;
     const size_t sb = 2ull * h->n_fluid * sizeof(double);
     if (H.magic != STATE_MAGIC || H.hash != param_hash(h->p, h->n_fluid) || H.fbytes != fb || H.xbytes != xb ||
         H.sbytes != sb || bytes < sizeof(H) + fb + xb + sb)

@@ -330,11 +330,15 @@ class Solver:
         self._check(lib().lbm_ms_residual(self.h, ctypes.byref(r)))
         return r.value
 
-    def converge(self, tol: float, max_steps: int, check_every: int = 100):
+    def converge(self, tol: float, max_steps: int, check_every: int = 100,
+                 raise_on_fail: bool = True):
+        """Returns (steps, residual), or (steps, residual, status) with raise_on_fail=False."""
         steps = ctypes.c_int64(0)
         r = ctypes.c_double(0.0)
         rc = lib().lbm_ms_converge(self.h, tol, int(max_steps), int(check_every),
                                    ctypes.byref(steps), ctypes.byref(r))
+        if not raise_on_fail:
+            return steps.value, r.value, rc
         self._check(rc)
         return steps.value, r.value
 

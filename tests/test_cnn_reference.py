@@ -53,3 +53,31 @@ def test_gradients_match_finite_differences():
         Lm[li][1][0] -= h
         fd = (loss_of(Lp) - loss_of(Lm)) / (2 * h)
         assert abs(fd - grads[li][1][0]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_feature_profiles_reduce_to_special_cases():
+    """No solid: the porosity-weighted profile is the profile itself; every column half solid:
+    its increments double."""
+    rng = np.random.default_rng(3)
+    W, H = 12, 8
+    X_in = np.array([[0.5, 0.3, 0.2]])
+    prof = X_in[:, :2, None] - np.cumsum(rng.uniform(0, 1e-3, (1, 2, W)), axis=2)
+    prof[:, :, 0] = X_in[:, :2]
+    f, base = ref.features(np.zeros((1, H, W), np.uint8), X_in, np.array([1.0]), prof)
+    assert np.allclose(base, prof, atol=1e-15) and np.all(f[0, 7] == 1.0)
+    solid = np.zeros((1, H, W), np.uint8)
+    solid[:, ::2, :] = 1
+    f, base = ref.features(solid, X_in, np.array([1.0]), prof)
+    assert np.allclose(base - X_in[:, :2, None], 2.0 * (prof - X_in[:, :2, None]), atol=1e-15)
+    assert np.allclose(f[0, 5:7], ((base[0] - X_in[0, :2, None]) / 0.01)[:, None, :], atol=1e-12)
+    assert np.array_equal(f[0, 0], 1.0 - solid[0]) and np.all(f[0, 3] == 0.5)
+    assert np.all(f[0, 1] == 0.5) and np.all(f[0, 2] == 0.3) and np.all(f[0, 7] == 0.5)
+    assert f[0, 4, 0, 0] == 0.0 and f[0, 4, 0, -1] == 1.0
+
+
+def test_assemble_stays_on_the_simplex():
+    rng = np.random.default_rng(4)
+    pred = rng.normal(0.0, 5.0, (2, 2, 4, 6))
+    prof = np.full((2, 2, 6), 0.4)
+    X = ref.assemble(pred, prof, 0.1, 1e-6)
+    assert np.all(X >= 1e-6 - 1e-15) and np.allclose(X.sum(axis=1), 1.0, atol=1e-15)

@@ -80,3 +80,35 @@ def test_adam_matches_definition():
     # first Adam step moves every parameter by -lr * sign(g) (bias-corrected moments)
     for a, b in zip(net.params(), p0):
         assert torch.allclose(a - b, torch.full_like(a, -1e-2), atol=1e-7)
+
+
+def test_features_match_reference():
+    rng = np.random.default_rng(11)
+    B, H, W = 3, 37, 50
+    solid = (rng.random((B, H, W)) < 0.45).astype(np.uint8)
+    X_in = rng.dirichlet((6.0, 3.0, 1.0), size=B)
+    j = rng.uniform(0.0, 2.0, B)
+    prof = X_in[:, :2, None] + np.cumsum(rng.normal(0.0, 1e-3, (B, 2, W)), axis=2)
+    prof[:, :, 0] = X_in[:, :2]
+    dev = lambda a, t: torch.tensor(a, dtype=t, device="cuda")  # noqa: E731
+    for case in range(2):
+        if case == 1:
+            solid[1, :, 7] = 1  # a column of solid only: phi clamps at 1/H
+        feat, base = cnn.features(dev(solid, torch.uint8), dev(X_in, torch.float64),
+                                  dev(j, torch.float64), dev(prof, torch.float64))
+        rf, rb = ref.features(solid, X_in, j, prof)
+        assert np.max(np.abs(base.cpu().numpy() - rb)) <= 1e-14
+        feat = feat.cpu().double().numpy()
+        assert np.max(np.abs(feat - rf)) <= 2e-6 * max(1.0, np.max(np.abs(rf))), case
+
+
+def test_assemble_matches_reference():
+    rng = np.random.default_rng(12)
+    B, H, W = 2, 9, 30
+    pred = rng.normal(0.0, 3.0, (B, 2, H, W)).astype(np.float32)
+    prof = rng.dirichlet((6.0, 3.0, 1.0), size=(B, W)).transpose(0, 2, 1)[:, :2].copy()
+    X = cnn.assemble(torch.tensor(pred, device="cuda"),
+                     torch.tensor(prof, device="cuda")).cpu().numpy()
+    r = ref.assemble(pred.astype(np.float64), prof, cnn.SCALE, 1e-6)
+    assert np.max(np.abs(X - r)) <= 1e-7
+    assert np.all(X >= 1e-6 - 1e-15) and np.allclose(X.sum(axis=1), 1.0, atol=1e-14)

@@ -210,16 +210,17 @@ def test_init_from_device_and_host_fields_agree():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
-def test_checkpoint_restart_is_bitwise(precision):
+@pytest.mark.parametrize("precision,shift", [("fp64", lbm_ms.SHIFT_GLOBAL), ("fp32", lbm_ms.SHIFT_GLOBAL),
+                                             ("bf16", lbm_ms.SHIFT_GLOBAL), ("bf16", lbm_ms.SHIFT_NODE)])
+def test_checkpoint_restart_is_bitwise(precision, shift):
     case = _percolating_2d(70, 30, seed0=6, tau_ref=3.0)
-    s, _ = _pair(case, precision=precision)
+    s, _ = _pair(case, precision=precision, shift_mode=shift)
     s.init()
     s.step(30)
     blob = s.save_state()
     s.step(25)
     ref = s.get_populations()
-    s2, _ = _pair(case, precision=precision)
+    s2, _ = _pair(case, precision=precision, shift_mode=shift)
     s2.load_state(blob)
     s2.step(25)
     assert np.array_equal(s2.get_populations(), ref)
@@ -229,6 +230,7 @@ def test_checkpoint_restart_is_bitwise(precision):
     ("fp32", lbm_ms.SHIFT_GLOBAL, 2e-6),
     ("fp16", lbm_ms.SHIFT_GLOBAL, 2e-4),
     ("bf16", lbm_ms.SHIFT_GLOBAL, 2e-3),
+    ("fp32", lbm_ms.SHIFT_NODE, 2e-6),
     ("fp16", lbm_ms.SHIFT_NODE, 2e-4),
     ("bf16", lbm_ms.SHIFT_NODE, 2e-3),
 ])
@@ -264,3 +266,31 @@ def test_full_size_porous_2d_fp64_and_fp32():
         print("full size %s: max |dX| after 3 steps = %.3e" % (precision, err))
         assert err <= tol
         s.close()
+
+
+@pytest.mark.parametrize("precision,x_tol,eta_tol", [
+    ("fp32", 1e-7, 1e-8),
+    ("bf16", 2e-4, 2e-5),
+    ("fp16", 2e-4, 2e-5),
+])
+def test_node_shift_steady_state_matches_fp64(precision, x_tol, eta_tol):
+    """Steady state of the reduced-precision NODE-shift storage against the FP64 path (itself
+    pinned to the oracle above).  The moment stays in FP64, so the rounding of the stored
+    deviations does not stall the slowest mode: the converged fields agree far below the
+    distance to steady state that a residual of 1e-8 leaves."""
+    case = _percolating_2d(64, 40, seed0=31, tau_ref=3.0, j_A_cm2=1.5)
+    ref = lbm_ms.Solver(case, precision="fp64", ms_mode=lbm_ms.STOICH)
+    ref.init()
+    n_ref, r_ref = ref.converge(1e-12, 2_000_000, check_every=1000)
+    s = lbm_ms.Solver(case, precision=precision, shift_mode=lbm_ms.SHIFT_NODE, ms_mode=lbm_ms.STOICH)
+    s.init()
+    # a 16-bit state may stop short of 1e-12 at its rounding floor; it runs as long as FP64 did
+    n, r, rc = s.converge(1e-12, n_ref, check_every=1000, raise_on_fail=False)
+    assert rc in (lbm_ms.OK, lbm_ms.E_NOT_CONVERGED)
+    dX = np.max(np.abs(s.get_fields() - ref.get_fields()))  # solid nodes read 0 in both
+    deta = abs(s.overpotential() - ref.overpotential())
+    print("%s node shift: %d steps (FP64 %d), r %.2e, max |dX| %.3e, |d eta| %.3e V"
+          % (precision, n, n_ref, r, dX, deta))
+    assert dX <= x_tol and deta <= eta_tol
+    s.close()
+    ref.close()
