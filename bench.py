@@ -85,7 +85,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--shift", default="global", choices=["global", "node"])
-    ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d"])
+    ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--chunk-z", type=int, default=0)
@@ -103,6 +103,8 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch_2d":
+        return run_batch(args)
     if args.workload == "porous_2d":
         case = inputs.porous_2d()
         desc = ("porous anode slice D2Q9 1024x1024, overlapping disks r~U[4,12], void fraction "
@@ -164,7 +166,7 @@ def main(argv=None):
             "lattice": case.lattice,
             "nx": case.nx, "ny": case.ny, "nz": case.nz,
             "fluid_nodes": n_fluid,
-            "storage": args.precision + ("" if args.precision in ("fp32", "fp64") else "-" + args.shift + "-shift"),
+            "storage": args.precision + ("" if args.precision == "fp64" else "-" + args.shift + "-shift"),
             "ms_solve": "fp64",
             "tau_ref": case.tau_ref,
             "check_every": args.check_every,
@@ -190,6 +192,90 @@ def main(argv=None):
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(line), flush=True)
     s.close()
+    return 0
+
+
+def run_batch(args):
+    """64 ragged porous slices (sides 256..1024, one inlet composition, j ~ U[0, 2] A/cm^2) in one
+    launch per step, hipGraph chunks of --check-every steps with the per-instance residual check
+    between them, autotuned tile height."""
+    import torch
+    from paper_1809_01600_amd import autotune, inputs, lbm_ms
+    cases = inputs.batch_2d(tau_ref=3.0,
+                            accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+    shift = lbm_ms.SHIFT_NODE if args.shift == "node" else lbm_ms.SHIFT_GLOBAL
+    b = lbm_ms.Batch(cases, precision=args.precision, shift_mode=shift)
+    tile = autotune.tune_batch(b)
+    b.use_graphs(True)
+    b.init()
+    _, n_fluid, n_tiles = b.stats()
+    b.converge(0.0, args.warmup, check_every=args.check_every, raise_on_fail=False)
+    torch.cuda.synchronize()
+    K = args.steps
+    t0 = time.perf_counter()
+    steps, r, rc = b.converge(0.0, K, check_every=args.check_every, raise_on_fail=False)
+    eta = b.overpotential()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    active, n_fluid_end, _ = b.stats()
+    failed = int(sum(1 for v in b.status if v not in (lbm_ms.OK, lbm_ms.E_NOT_CONVERGED)))
+    # node updates actually done (an instance that failed its check left the work list)
+    updates = float(sum(int(st) * int(b.instance(k).get_info().n_fluid) for k, st in enumerate(steps)))
+    kernel_ms = b.time_steps(min(K, 200)) / min(K, 200)
+    bytes_per_launch = BYTES_PER_NODE[("D2Q9", args.precision)] * n_fluid_end
+    if shift == lbm_ms.SHIFT_NODE:
+        bytes_per_launch += NODE_SHIFT_BYTES * n_fluid_end
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    value = 2.0 * updates / elapsed / 1e6
+    order = sorted(range(len(cases)), key=lambda k: cases[k].j_A_cm2)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "species-MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else args.precision.replace("fp", "f"),
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of 64 porous slices D2Q9, sides ~U{256..1024}, void fraction "
+                        "~U[0.3,0.5], disks r~U[3,12], seeds 4000+k, X_in=(0.6,0.3,0.1), "
+                        "j~U[0,2] A/cm^2, tau_ref 3, one launch per step",
+            "instances": len(cases),
+            "fluid_nodes": int(n_fluid),
+            "tiles": int(n_tiles),
+            "storage": args.precision + ("" if args.precision == "fp64" else "-" + args.shift + "-shift"),
+            "ms_solve": "fp64",
+            "check_every": args.check_every,
+            "graphs": True,
+            "tile": [64, int(tile[0])],
+            "active_at_end": int(active),
+            "failed_checks": failed,
+            "node_mlups": round(updates / elapsed / 1e6, 1),
+            "eta_V_by_j": [[round(cases[k].j_A_cm2, 4), float(eta[k])] for k in order],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("batch_2d_%s_%s" % (args.precision, args.shift), kernel_hash()),
+            "kernel": "k_step2d",
+            "kernel_us": round(kernel_ms * 1e3, 3),
+            "bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu:
+        small = min(range(len(cases)), key=lambda k: cases[k].nx)
+        line["cpu_baseline"] = cpu_baseline(cases[small], args.cpu_steps)
+    print(json.dumps(line), flush=True)
+    b.close()
     return 0
 
 

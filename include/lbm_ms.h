@@ -238,6 +238,10 @@ int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device);
 /* nsteps steps of every active instance (one launch per step; asynchronous). */
 int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps);
 
+/* nsteps eager steps bracketed by HIP events on the batch's launch stream; *ms = elapsed
+ * milliseconds (synchronizes). */
+int lbm_ms_batch_time_steps(lbm_ms_batch_t b, int64_t nsteps, double* ms);
+
 /* Steps in hipGraph-captured chunks of check_every until every instance's residual (as
  * lbm_ms_residual) is below tol or max_steps is reached.  An instance whose check fails
  * (E_NEG_FRACTION when its current exceeds what its pores can supply, E_DIVERGED, E_TAU_CLAMP)

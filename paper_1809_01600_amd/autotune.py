@@ -77,7 +77,6 @@ def tune(solver, steps: int = 100, warmup: int = 10, use_cache: bool = True):
 def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
     """Pick the fastest tile height for a batch.  Tuning (re)initializes the batch to the uniform
     inlet composition and advances it; initialize again before a solve."""
-    import torch
     p = batch.params
     sizes = sorted((c.nx, c.ny) for c in batch.cases)
     key = _key("batch", "D2Q9", p.precision, p.shift_mode,
@@ -91,13 +90,7 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
     for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9, p.precision):
         batch.set_tile(ty)
         batch.step(warmup)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        batch.step(steps)
-        e1.record()
-        e1.synchronize()
-        timings[ty] = e0.elapsed_time(e1) / steps
+        timings[ty] = batch.time_steps(steps) / steps
     best = min(timings, key=timings.get)
     batch.set_tile(best)
     data = _load()

@@ -1337,6 +1337,30 @@ int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps)
     return b->leave(rc);
 }
 
+int lbm_ms_batch_time_steps(lbm_ms_batch_t b, int64_t nsteps, double* ms)
+{
+    if (!b || !ms || nsteps < 0) return LBM_MS_E_ARG;
+    for (auto* h : b->inst)
+        if (!h->ready) return b->fail(LBM_MS_E_STATE, "init first");
+    hipEvent_t e0, e1;
+    int rc = b->hip(hipEventCreate(&e0), "event");
+    if (rc) return rc;
+    rc = b->hip(hipEventCreate(&e1), "event");
+    if (rc) { hipEventDestroy(e0); return rc; }
+    rc = b->enter();
+    if (!rc) rc = b->hip(hipEventRecord(e0, b->stream), "event record");
+    if (!rc) rc = b->step_eager(nsteps);
+    if (!rc) rc = b->hip(hipEventRecord(e1, b->stream), "event record");
+    rc = b->leave(rc);
+    if (!rc) rc = b->hip(hipEventSynchronize(e1), "event sync");
+    float t = 0.f;
+    if (!rc) rc = b->hip(hipEventElapsedTime(&t, e0, e1), "elapsed");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = t;
+    return rc;
+}
+
 int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int check_every,
                           int64_t* steps_taken, double* residual, int* status)
 {

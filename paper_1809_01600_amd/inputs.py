@@ -194,18 +194,26 @@ def porous_3d(n: int = 256, seed: int = 3, j_A_cm2: float = 1.0, r_lo: float = 3
 
 
 def batch_2d(count: int = 64, base_seed: int = 4000, side_lo: int = 256, side_hi: int = 1024,
-             j_hi: float = 2.0, tau_ref: float = 100.0):
-    """Ragged batch of square porous slices for one polarization curve (one X_in)."""
+             j_hi: float = 2.0, tau_ref: float = 100.0, accept=None):
+    """Ragged batch of square porous slices for one polarization curve (one X_in).  Instance k
+    draws from seed base_seed + k; if accept(solid) is given and rejects the geometry (say, no
+    pore path from inlet to outlet), it draws again from seed base_seed + k + 1000 a, a = 1, 2..."""
     cases = []
     for k in range(count):
-        rng = np.random.Generator(np.random.PCG64(base_seed + k))
-        side = int(rng.integers(side_lo, side_hi + 1))
-        por = float(rng.uniform(0.3, 0.5))
-        j = float(rng.uniform(0.0, j_hi))
-        solid = disks_2d(side, side, por, 3.0, 12.0, rng)
+        for attempt in range(100):
+            seed = base_seed + k + 1000 * attempt
+            rng = np.random.Generator(np.random.PCG64(seed))
+            side = int(rng.integers(side_lo, side_hi + 1))
+            por = float(rng.uniform(0.3, 0.5))
+            j = float(rng.uniform(0.0, j_hi))
+            solid = disks_2d(side, side, por, 3.0, 12.0, rng)
+            if accept is None or accept(solid):
+                break
+        else:
+            raise RuntimeError("no accepted geometry for instance %d" % k)
         cases.append(Case(name=f"batch_{k}", lattice="D2Q9", nx=side, ny=side, nz=1,
                           dx=1.0e-6, tau_ref=tau_ref, X_in=(0.6, 0.3, 0.1), j_A_cm2=j,
-                          solid=solid, seed=base_seed + k))
+                          solid=solid, seed=seed))
     return cases
 
 

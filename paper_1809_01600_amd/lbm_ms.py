@@ -129,6 +129,7 @@ _SIGNATURES = [
                                            _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
     ("lbm_ms_batch_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_ms_batch_step", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("lbm_ms_batch_time_steps", ctypes.c_int, [_VP, ctypes.c_int64, _DP]),
     ("lbm_ms_batch_converge", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_int64), _DP,
                                              ctypes.POINTER(ctypes.c_int)]),
@@ -475,6 +476,12 @@ class Batch:
 
     def step(self, n=1):
         self._check(lib().lbm_ms_batch_step(self.b, int(n)))
+
+    def time_steps(self, n):
+        """Milliseconds of n eager steps (HIP events on the batch's launch stream)."""
+        ms = ctypes.c_double(0.0)
+        self._check(lib().lbm_ms_batch_time_steps(self.b, int(n), ctypes.byref(ms)))
+        return ms.value
 
     def converge(self, tol, max_steps, check_every=100, raise_on_fail=True):
         """Returns (steps per instance, residual per instance, overall status); per-instance
