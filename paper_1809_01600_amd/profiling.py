@@ -5,7 +5,8 @@ summarizer of rocprofv3 CSV output.
   python -m paper_1809_01600_amd.profiling summarize <rocprofv3 output dir> [--kernel NAME]
   python -m paper_1809_01600_amd.profiling report --name NAME --key KEY --kernel K \
       --trace DIR --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \
-      --alg-bytes B --command "..."   (writes profiles/NAME.txt and profiles/traffic.json)
+      --alg-bytes B --command "..." [--counter-command "..."]
+      (writes profiles/NAME.txt and profiles/traffic.json)
 """
 
 from __future__ import annotations
@@ -100,7 +101,8 @@ def report(args) -> None:
     lines = []
     lines.append("rocprofv3 summary: %s" % args.name)
     lines.append("command (trace): %s" % args.command)
-    lines.append("counters: same program under rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE;")
+    lines.append("counters: %s" % (args.counter_command or
+                                   "same program under rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE"))
     lines.append("calibration: python3 -m paper_1809_01600_amd.profiling copy --mib %d --reps 5 under"
                  " the same two counters" % args.copy_mib)
     lines.append("")
@@ -154,6 +156,7 @@ def main(argv=None):
         r.add_argument("--" + a.replace("_", "-"), required=True)
     r.add_argument("--alg-bytes", type=float, required=True)
     r.add_argument("--copy-mib", type=int, default=1024)
+    r.add_argument("--counter-command", default="")
     args = ap.parse_args(argv)
     if args.cmd == "copy":
         run_copy(args.mib, args.reps)

@@ -74,8 +74,11 @@ def stoich_D(Dl: np.ndarray, X: np.ndarray) -> np.ndarray:
 
 
 def discrete_chain_stoich(Dl: np.ndarray, X_in, Q, n: int, tol: float = 1e-15) -> np.ndarray:
-    """Exact steady state of the D1Q3-reduced scheme with node-wise tau (derivation in
-    the design doc, 'discrete Stefan chain'): link flux Phi = Q everywhere and
+    """Exact steady state of the D1Q3-reduced scheme with node-wise tau.  At steady state every
+    link carries the outlet flux: Phi = f*_+(k) - f*_-(k+1) = Q.  A node's first moment relaxes
+    as J* = (1 - 1/tau) J, and the node's post-stream J is set by the neighbours' equilibria, so
+    the step across a link is the flux times the half-sum of the two nodes' resistances 1/D*
+    (D* = (tau - 1/2)/3):
 
         X_s(k) - X_s(k+1) = Q_s * (1/D*_s(k) + 1/D*_s(k+1)) / 2,   X_s(0) = X_in,s,
 
@@ -109,9 +112,15 @@ def discrete_chain_stoich(Dl: np.ndarray, X_in, Q, n: int, tol: float = 1e-15) -
 
 def exact_variance(sigma0_sq: float, tau: float, t: int) -> float:
     """Second moment of a pulse under the D1Q3 marginal of BGK diffusion with constant tau,
-    started from equilibrium on an unbounded lattice (derivation in the design doc, 'exact
-    variance'): sigma^2(t) = sigma0^2 + 2 D* t - (2/3) tau (tau - 1) (1 - (1 - 1/tau)^t),
-    D* = (tau - 1/2) / 3."""
+    started from equilibrium on an unbounded lattice:
+
+        sigma^2(t) = sigma0^2 + 2 D* t - (2/3) tau (tau - 1) (1 - (1 - 1/tau)^t),
+
+    with D* = (tau - 1/2) / 3.  Tracking the moments sum x^2 X and sum x J (J the first
+    velocity moment) through stream and collide gives this form: the variance grows at the BGK
+    diffusivity, and the position-flux correlation starts at zero (equilibrium start) and
+    approaches its steady value geometrically with the factor (1 - 1/tau) per step, which is
+    the transient term."""
     D = (tau - 0.5) / 3.0
     q = 1.0 - 1.0 / tau
     return sigma0_sq + 2.0 * D * t - (2.0 / 3.0) * tau * (tau - 1.0) * (1.0 - q ** t)

@@ -4,6 +4,8 @@ Every test here checks the oracle against something other than itself: closed fo
 discrete identities, conservation, symmetry, or a library routine.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -37,11 +39,28 @@ def run_to_steady(o, window=2000, tol=1e-15, max_steps=2_000_000):
 # velocity sets (Eq. 2, Eq. 9; D3Q19 moments)
 # ----------------------------------------------------------------------------------------------
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
 def test_d2q9_matches_eq2_eq9():
+    """The paper's printed D2Q9 lattice (Eq. 2 order, Eq. 9 weights), tests/golden/d2q9_lattice.txt."""
+    g = np.loadtxt(os.path.join(GOLDEN, "d2q9_lattice.txt"))
     e, w = oracle.velocities("D2Q9")
-    assert e[:, :2].tolist() == [[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1],
-                                 [1, 1], [-1, 1], [-1, -1], [1, -1]]
-    assert np.allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, rtol=0, atol=1e-16)
+    assert e[:, :2].tolist() == g[:, 1:3].astype(int).tolist()
+    assert np.allclose(w, g[:, 3] / g[:, 4], rtol=0, atol=1e-16)
+
+
+def test_constants_are_the_papers():
+    """Gas constant (nomenclature) and Faraday constant (Eq. 39), tests/golden/constants.txt."""
+    vals = {}
+    with open(os.path.join(GOLDEN, "constants.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, value = line.split()[:2]
+                vals[name] = float(value)
+    assert oracle.R_GAS == vals["R_GAS"] and oracle.FARADAY == vals["FARADAY"]
+    c = inputs.stefan_tube()
+    assert c.n_electrons == vals["n_electrons"]
 
 
 @pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19)])
