@@ -360,6 +360,17 @@ __device__ inline uint32_t pull_node(const StepArgs& a, int x, int y, int z, lon
     return nb;
 }
 
+// 1/d in FP64 from the hardware reciprocal estimate and two Newton steps (each doubles the
+// number of correct bits), without the scaling and fix-up of a correctly rounded division; the
+// operands here are positive and far from the denormal and overflow ranges.
+__device__ inline double rcp64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    r = r * (2.0 - d * r);
+    return r;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Maxwell-Stefan flux solve and relaxation times (FP64)
 // ---------------------------------------------------------------------------------------------
@@ -383,7 +394,7 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     double n0 = 0.0, n1 = 0.0;
     if (a.ms_mode == 0) {
         // Eq. 34 with Gamma = I: J = -[B]^-1 grad X (Cramer's rule), then |J| per species
-        const double rdet = 1.0 / (B00 * B11 - B01 * B10);
+        const double rdet = rcp64(B00 * B11 - B01 * B10);
         double q0 = 0.0, q1 = 0.0;
 #pragma unroll
         for (int dd = 0; dd < DIMS; ++dd) {
@@ -399,7 +410,7 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     if (a.ms_mode == 0) {
         // flux-norm ratios |N_2|/|N_1| and |N_1|/|N_2| through one reciprocal
         const double u = n1 + a.eps1, v = n0 + a.eps0;
-        const double ruv = 1.0 / (u * v);
+        const double ruv = rcp64(u * v);
         r21 = u * u * ruv;
         r12 = v * v * ruv;
     }
@@ -408,8 +419,8 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     const double inv1 = (X0 - X1 * a.sgn12 * r12) * a.iD12 + X2 * a.iD23;
     // Eq. 25 with c_s^2 = 1/3: tau = 3 D + 1/2, so 1/tau = (1/D) / (3 + (1/D) / 2); the clamp
     // tau in [tau_min, tau_max] is applied as 1/tau in [1/tau_max, 1/tau_min]
-    double w0 = inv0 / (3.0 + 0.5 * inv0);
-    double w1 = inv1 / (3.0 + 0.5 * inv1);
+    double w0 = inv0 * rcp64(3.0 + 0.5 * inv0);
+    double w1 = inv1 * rcp64(3.0 + 0.5 * inv1);
     bool h = false;
     if (!(w0 <= a.om_hi)) { w0 = a.om_hi; h = true; }
     else if (w0 < a.om_lo) { w0 = a.om_lo; h = true; }

@@ -101,11 +101,18 @@ __device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[D2Q9::
 // fluid nodes outside them whose moments the tile's gradients read (the halo).  Entries are LDS
 // coordinates (cx, cy) of the (TX + 2) x (TY + 2) moment tile, packed as cy << 8 | cx.  Every
 // lane works on a fluid node; two memory round trips (staged index map, then all population
-// loads of the tile and its halo at once).  Workgroup = 32 TY lanes, so a lane holds at most
-// two of the tile's 64 TY nodes.
+// loads of the tile and its halo at once).  Workgroup = 32 TY lanes and a lane holds at most one
+// own node: the host splits a tile with more fluid nodes into parts, each listing the others'
+// nodes it needs as halo.  One node per lane keeps the register count low enough for eight
+// waves per SIMD.
 // ---------------------------------------------------------------------------------------------
+// Global-shift FP32 and 16-bit instantiations fit in 64 VGPRs: ask for eight waves per SIMD
+// (minimum workgroups per CU = 8 waves x 4 SIMDs / (TY / 2) waves per workgroup).
+template <int P, bool NS>
+constexpr int step2d_min_blocks(int ty) { return (P != P_F64 && !NS) ? 64 / ty : 1; }
+
 template <int P, bool NS, int TY>
-__global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__ insts,
+__global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_step2d(const StepArgs* __restrict__ insts,
                                                     const int4* __restrict__ tiles,
                                                     const unsigned* __restrict__ ent)
 {
@@ -125,39 +132,31 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
     const StepArgs& a = insts[t0.z];
     const int x0 = t0.x, y0 = t0.y;
     // entry lists first (they depend only on the tile record), then the staged index map
-    const bool two = t1.y > BS;  // workgroup-uniform: a second own node per lane
     const unsigned dummy = (1u << 8) | 1u;
-    unsigned pe[3];
-    pe[0] = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
-    pe[1] = two && threadIdx.x + BS < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x + BS) * 4u) : dummy;
-    pe[2] = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
+    const unsigned pe0 = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
+    const unsigned pe2 = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
     if constexpr (NS)
         stage_plane_refs<RX, RY>(a, x0, y0, sI, sC);
     else
         stage_plane<RX, RY>(a, x0, y0, 0, sI);
     __syncthreads();
 
-    // own nodes (entries t and t + BS) and the first halo entry: all loads issued together
-    CT f[2][2][L::Q];
-    double X0[2] = {0.0, 0.0}, X1[2] = {0.0, 0.0};
-    int io[2] = {-1, -1}, cxo[2], cyo[2];
-    uint32_t nbo[2] = {0u, 0u};
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        cxo[u] = pe[u] & 255u;
-        cyo[u] = pe[u] >> 8;
-        if (u == 1 && !two) break;
-        const bool job = threadIdx.x + u * BS < (unsigned)t1.y;
-        io[u] = job ? sI[(cyo[u] + 1) * RX + cxo[u] + 1] : -1;
-        const int x = x0 + cxo[u] - 1;
+    // the lane's own node (at most one: the host splits denser tiles) and its first halo entry:
+    // all loads issued together
+    CT f[2][L::Q];
+    double X0 = 0.0, X1 = 0.0;
+    const int cxo = pe0 & 255u, cyo = pe0 >> 8;
+    const int io = threadIdx.x < (unsigned)t1.y ? sI[(cyo + 1) * RX + cxo + 1] : -1;
+    uint32_t nbo;
+    {
+        const int x = x0 + cxo - 1;
         int si[L::Q];
-        nbo[u] = lds_sources<L, RX, RY, 1>(sI, -2, cxo[u] + 1, cyo[u] + 1, x, a.nx, io[u], si);
-        gather2d<P, NS, RX, RY>(a, io[u] < 0 ? 0 : io[u], si, io[u] >= 0 && x == 0,
-                                io[u] >= 0 && x == a.nx - 1, f[u], X0[u], X1[u], sC, cxo[u] + 1,
-                                cyo[u] + 1);
+        nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
+        gather2d<P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && x == 0, io >= 0 && x == a.nx - 1,
+                                f, X0, X1, sC, cxo + 1, cyo + 1);
     }
     if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
-        const int cx = pe[2] & 255u, cy = pe[2] >> 8;
+        const int cx = pe2 & 255u, cy = pe2 >> 8;
         const bool job = threadIdx.x < (unsigned)t1.w;
         const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
         const int x = x0 + cx - 1;
@@ -172,7 +171,7 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
             sX[1][cy][cx] = h1;
         }
     }
-    // remaining halo entries (only where the tile wraps onto itself in y)
+    // remaining halo entries (a tile that wraps onto itself in y, or one part of a split tile)
     for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
         const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
         const int cx = pw & 255u, cy = pw >> 8;
@@ -186,33 +185,26 @@ __global__ __launch_bounds__(32 * TY) void k_step2d(const StepArgs* __restrict__
         sX[0][cy][cx] = h0;
         sX[1][cy][cx] = h1;
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        if (io[u] >= 0) {
-            sX[0][cyo[u]][cxo[u]] = X0[u];
-            sX[1][cyo[u]][cxo[u]] = X1[u];
-        }
+    if (io >= 0) {
+        sX[0][cyo][cxo] = X0;
+        sX[1][cyo][cxo] = X1;
     }
     __syncthreads();
 
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        if (io[u] < 0) continue;
-        const int cx = cxo[u], cy = cyo[u];
-        const uint32_t nb = nbo[u];
-        double g0[3], g1[3];
-        const bool xp = nb & NB_XP, xm = nb & NB_XM, yp = nb & NB_YP, ym = nb & NB_YM;
-        g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0[u], sX[0][cy][cx - 1]);
-        g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1[u], sX[1][cy][cx - 1]);
-        g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0[u], sX[0][cy - 1][cx]);
-        g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1[u], sX[1][cy - 1][cx]);
-        g0[2] = g1[2] = 0.0;
-        double om0, om1;
-        bool hit;
-        ms_relax<2>(a, X0[u], X1[u], g0, g1, x0 + cx - 1 == a.nx - 1, om0, om1, hit);
-        if (hit) gstore<unsigned>(a.flags, 0u, 1u);
-        collide_store<L, P, NS>(a, io[u], f[u], X0[u], X1[u], om0, om1);
-    }
+    if (io < 0) return;
+    const int cx = cxo, cy = cyo;
+    double g0[3], g1[3];
+    const bool xp = nbo & NB_XP, xm = nbo & NB_XM, yp = nbo & NB_YP, ym = nbo & NB_YM;
+    g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
+    g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
+    g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
+    g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
+    g0[2] = g1[2] = 0.0;
+    double om0, om1;
+    bool hit;
+    ms_relax<2>(a, X0, X1, g0, g1, x0 + cx - 1 == a.nx - 1, om0, om1, hit);
+    if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+    collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -41,6 +41,16 @@ size_t elem_bytes(int prec)
     }
 }
 
+// Bounds of the 2D work lists for any tile height TY >= 4: a 64 x TY tile splits into at most two
+// parts (64 TY nodes, 32 TY lanes); own entries total at most nx ny; each part lists at most
+// (64 + 2)(TY + 2) halo entries, which is largest per node at TY = 4.
+void tile_caps(int nx, int ny, size_t* tiles, size_t* ents)
+{
+    const size_t t4 = (size_t)((nx + 63) / 64) * (size_t)((ny + 3) / 4);
+    *tiles = 2 * t4;
+    *ents = (size_t)nx * ny + 2 * t4 * 66 * 6 + 4096;
+}
+
 bool node_shift(const lbm_ms_params& p)
 {
     return p.precision != LBM_MS_FP64 && p.shift_mode == LBM_MS_SHIFT_NODE;
@@ -104,10 +114,7 @@ Layout layout(const lbm_ms_params& p)
     // 2D work lists: tiles of 64 x TY (TY >= 4) and their entries
     L.tile_cap = 0;
     L.ent_cap = 0;
-    if (p.lattice == LBM_MS_D2Q9) {
-        L.tile_cap = (size_t)((p.nx + 63) / 64) * (size_t)((p.ny + 3) / 4);
-        L.ent_cap = 3 * N + 4096;
-    }
+    if (p.lattice == LBM_MS_D2Q9) tile_caps(p.nx, p.ny, &L.tile_cap, &L.ent_cap);
     L.inst = take(2 * sizeof(StepArgs));
     L.tiles = take(L.tile_cap * 2 * sizeof(int4));
     L.ent = take(L.ent_cap * sizeof(uint32_t));
@@ -325,29 +332,33 @@ void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, i
                     uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent)
 {
     const int TX = 64;
+    const size_t lanes = (size_t)32 * ty;  // workgroup size: one own node per lane
     auto fluid = [&](int x, int y) { return !solid[(size_t)y * nx + x]; };
     std::vector<uint8_t> mark((TX + 2) * (ty + 2));
+    std::vector<uint32_t> own;
+    static const int dxy[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
     for (int y0 = 0; y0 < ny; y0 += ty)
         for (int x0 = 0; x0 < nx; x0 += TX) {
-            const uint32_t own_off = ent_base + (uint32_t)ent.size();
-            std::fill(mark.begin(), mark.end(), 0);
-            auto is_own = [&](int cx, int cy) {
-                const int x = x0 + cx - 1, yr = y0 + cy - 1;
-                return cx >= 1 && cx <= TX && cy >= 1 && cy <= ty && x < nx && yr < ny && fluid(x, yr);
-            };
-            for (int cy = 1; cy <= ty; ++cy)
-                for (int cx = 1; cx <= TX; ++cx)
-                    if (is_own(cx, cy)) {
-                        ent.push_back((uint32_t)(cy << 8 | cx));
-                        mark[cy * (TX + 2) + cx] = 1;
-                    }
-            const uint32_t own_cnt = ent_base + (uint32_t)ent.size() - own_off;
-            if (own_cnt == 0) continue;
-            const uint32_t halo_off = ent_base + (uint32_t)ent.size();
-            static const int dxy[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+            own.clear();
             for (int cy = 1; cy <= ty; ++cy)
                 for (int cx = 1; cx <= TX; ++cx) {
-                    if (!is_own(cx, cy)) continue;
+                    const int x = x0 + cx - 1, yr = y0 + cy - 1;
+                    if (x < nx && yr < ny && fluid(x, yr)) own.push_back((uint32_t)(cy << 8 | cx));
+                }
+            // parts of at most `lanes` own nodes (raster order, so a split runs along rows); each
+            // part's halo: the fluid axis neighbours of its nodes outside the part, other parts
+            // of the tile included
+            for (size_t start = 0; start < own.size(); start += lanes) {
+                const size_t stop = std::min(own.size(), start + lanes);
+                std::fill(mark.begin(), mark.end(), 0);
+                const uint32_t own_off = ent_base + (uint32_t)ent.size();
+                for (size_t e = start; e < stop; ++e) {
+                    ent.push_back(own[e]);
+                    mark[(own[e] >> 8) * (TX + 2) + (own[e] & 255u)] = 1;
+                }
+                const uint32_t halo_off = ent_base + (uint32_t)ent.size();
+                for (size_t e = start; e < stop; ++e) {
+                    const int cx = own[e] & 255u, cy = own[e] >> 8;
                     for (auto& d : dxy) {
                         const int hx = cx + d[0], hy = cy + d[1];
                         const int gx = x0 + hx - 1;
@@ -358,9 +369,10 @@ void build_tiles_2d(int nx, int ny, int ty, const std::vector<uint8_t>& solid, i
                         ent.push_back((uint32_t)(hy << 8 | hx));
                     }
                 }
-            const uint32_t halo_cnt = ent_base + (uint32_t)ent.size() - halo_off;
-            tiles.push_back(make_int4(x0, y0, instance, 0));
-            tiles.push_back(make_int4((int)own_off, (int)own_cnt, (int)halo_off, (int)halo_cnt));
+                const uint32_t halo_cnt = ent_base + (uint32_t)ent.size() - halo_off;
+                tiles.push_back(make_int4(x0, y0, instance, 0));
+                tiles.push_back(make_int4((int)own_off, (int)(stop - start), (int)halo_off, (int)halo_cnt));
+            }
         }
 }
 
@@ -372,7 +384,7 @@ bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>
         const int4 r = tiles[t + 1];
         if (r.x < 0 || r.y < 0 || r.z < 0 || r.w < 0) return false;
         if ((size_t)r.x + (size_t)r.y > n_ent || (size_t)r.z + (size_t)r.w > n_ent) return false;
-        if (r.y > 2 * 32 * ty) return false;  // a lane holds at most two own nodes
+        if (r.y > 32 * ty) return false;  // a lane holds at most one own node
         for (int e = 0; e < r.y + r.w; ++e) {
             const uint32_t v = ent[e < r.y ? (size_t)r.x + e : (size_t)r.z + (e - r.y)];
             const uint32_t cx = v & 255u, cy = v >> 8;
@@ -386,7 +398,7 @@ bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>
 int default_tile_y(const lbm_ms_params& p)
 {
     if (p.tile_y > 0) return p.tile_y;
-    if (p.lattice == LBM_MS_D2Q9) return p.ny >= 16 ? 16 : (p.ny >= 8 ? 8 : 4);
+    if (p.lattice == LBM_MS_D2Q9) return p.ny >= 8 ? 8 : 4;
     return p.precision == LBM_MS_FP64 ? 4 : 8;
 }
 
@@ -1165,8 +1177,10 @@ bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
         if (b == 0 || !inst[k].solid) return false;
         const size_t o = take(b);
         if (offs) offs->push_back(o);
-        tc += (size_t)((inst[k].nx + 63) / 64) * (size_t)((inst[k].ny + 3) / 4);
-        ec += 3ull * inst[k].nx * inst[k].ny + 4096;
+        size_t t = 0, e = 0;
+        tile_caps(inst[k].nx, inst[k].ny, &t, &e);
+        tc += t;
+        ec += e;
     }
     const size_t ot = take(2ull * count * sizeof(StepArgs));
     const size_t oti = take(tc * 2 * sizeof(int4));
