@@ -385,6 +385,7 @@ bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>
         if (r.x < 0 || r.y < 0 || r.z < 0 || r.w < 0) return false;
         if ((size_t)r.x + (size_t)r.y > n_ent || (size_t)r.z + (size_t)r.w > n_ent) return false;
         if (r.y > 32 * ty) return false;  // a lane holds at most one own node
+        if (r.z != r.x + r.y) return false;  // halo entries follow the own entries
         for (int e = 0; e < r.y + r.w; ++e) {
             const uint32_t v = ent[e < r.y ? (size_t)r.x + e : (size_t)r.z + (e - r.y)];
             const uint32_t cx = v & 255u, cy = v >> 8;
