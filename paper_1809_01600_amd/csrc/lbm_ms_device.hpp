@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace lbmms {
@@ -270,14 +271,17 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
             g[1][k] = anti ? -g[1][o] : g[1][k];
         }
     }
-    double S0 = 0.0, S1 = 0.0;
+    // the sum of small terms: FP64 for FP32 deviations; FP32 for 16-bit ones, whose own rounding
+    // (about 1e-3 of each term) dwarfs that of an FP32 sum
+    using AT = typename std::conditional<P == P_F32, double, float>::type;
+    AT S0 = 0, S1 = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        S0 += (double)((float)L::w[k] * dc[0][k]) + (double)g[0][k];
-        S1 += (double)((float)L::w[k] * dc[1][k]) + (double)g[1][k];
+        S0 += (AT)((float)L::w[k] * dc[0][k]) + (AT)g[0][k];
+        S1 += (AT)((float)L::w[k] * dc[1][k]) + (AT)g[1][k];
     }
-    X0 = co0 + S0;
-    X1 = co1 + S1;
+    X0 = co0 + (double)S0;
+    X1 = co1 + (double)S1;
     const float s0 = (float)S0, s1 = (float)S1;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -459,19 +463,20 @@ __device__ inline void collide_store(const StepArgs& a, int n,
     const unsigned base = (unsigned)n * ES;
     if constexpr (NS) {
         const float k0 = (float)(1.0 - om0), k1 = (float)(1.0 - om1);
-        double sh0 = 0.0, sh1 = 0.0;
+        using AT = typename std::conditional<P == P_F32, double, float>::type;
+        AT sh0 = 0, sh1 = 0;
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
             const raw r0 = C::enc(k0 * f[0][k], 0.f);
             const raw r1 = C::enc(k1 * f[1][k], 0.f);
-            sh0 += (double)C::dec(r0, 0.f);
-            sh1 += (double)C::dec(r1, 0.f);
+            sh0 += (AT)C::dec(r0, 0.f);
+            sh1 += (AT)C::dec(r1, 0.f);
             const unsigned off = base + (unsigned)k * plane;
             gstore<raw>(fout, off, r0);
             gstore<raw>(fout, off + spec, r1);
         }
-        gstore<double>(a.xout, (unsigned)n * 8u, X0 - sh0);
-        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 - sh1);
+        gstore<double>(a.xout, (unsigned)n * 8u, X0 - (double)sh0);
+        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 - (double)sh1);
         return;
     }
     const CT o0 = (CT)om0, o1 = (CT)om1;
