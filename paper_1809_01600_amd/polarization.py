@@ -4,7 +4,7 @@ batch (one launch per step, hipGraph chunks, converged instances leave the work 
 past its limiting current leaves with E_NEG_FRACTION).
 
     python -m paper_1809_01600_amd.polarization --count 64 --side-lo 64 --side-hi 256 \\
-        --tol 1e-9 --out gpurun_out/polarization.json
+        --tol 1e-9 --out polarization.json
 """
 
 from __future__ import annotations
