@@ -10,6 +10,7 @@
 // solid voxels cost no population traffic while a wavefront's loads and stores stay contiguous
 // along x.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "lbm_ms_device.hpp"
 #include "lbm_ms_kernels.hpp"
@@ -141,70 +142,80 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
         stage_plane<RX, RY>(a, x0, y0, 0, sI);
     __syncthreads();
 
-    // the lane's own node (at most one: the host splits denser tiles) and its first halo entry:
-    // all loads issued together
-    CT f[2][L::Q];
-    double X0 = 0.0, X1 = 0.0;
-    const int cxo = pe0 & 255u, cyo = pe0 >> 8;
-    const int io = threadIdx.x < (unsigned)t1.y ? sI[(cyo + 1) * RX + cxo + 1] : -1;
-    uint32_t nbo;
-    {
-        const int x = x0 + cxo - 1;
-        int si[L::Q];
-        nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
-        gather2d<P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && x == 0, io >= 0 && x == a.nx - 1,
-                                f, X0, X1, sC, cxo + 1, cyo + 1);
-    }
-    if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
-        const int cx = pe2 & 255u, cy = pe2 >> 8;
-        const bool job = threadIdx.x < (unsigned)t1.w;
-        const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
-        const int x = x0 + cx - 1;
-        int si[L::Q];
-        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
-        CT hf[2][L::Q];
-        double h0, h1;
-        gather2d<P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && x == 0, hi >= 0 && x == a.nx - 1,
-                                hf, h0, h1, sC, cx + 1, cy + 1);
-        if (job) {
+    // Tiles whose nodes and halo touch neither the inlet column nor the outlet column run a copy
+    // of the rest with the boundary rules compiled out (a workgroup-uniform branch).
+    const bool edge = x0 == 0 || x0 + TX + 1 >= a.nx;
+    auto rest = [&](auto bnd) {
+        constexpr bool BND = decltype(bnd)::value;
+        // the lane's own node (at most one: the host splits denser tiles) and its first halo entry:
+        // all loads issued together
+        CT f[2][L::Q];
+        double X0 = 0.0, X1 = 0.0;
+        const int cxo = pe0 & 255u, cyo = pe0 >> 8;
+        const int io = threadIdx.x < (unsigned)t1.y ? sI[(cyo + 1) * RX + cxo + 1] : -1;
+        uint32_t nbo;
+        {
+            const int x = x0 + cxo - 1;
+            int si[L::Q];
+            nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
+            gather2d<P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && BND && x == 0, io >= 0 && BND && x == a.nx - 1,
+                                    f, X0, X1, sC, cxo + 1, cyo + 1);
+        }
+        if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
+            const int cx = pe2 & 255u, cy = pe2 >> 8;
+            const bool job = threadIdx.x < (unsigned)t1.w;
+            const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
+            const int x = x0 + cx - 1;
+            int si[L::Q];
+            lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+            CT hf[2][L::Q];
+            double h0, h1;
+            gather2d<P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && BND && x == 0, hi >= 0 && BND && x == a.nx - 1,
+                                    hf, h0, h1, sC, cx + 1, cy + 1);
+            if (job) {
+                sX[0][cy][cx] = h0;
+                sX[1][cy][cx] = h1;
+            }
+        }
+        // remaining halo entries (a tile that wraps onto itself in y, or one part of a split tile)
+        for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
+            const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
+            const int cx = pw & 255u, cy = pw >> 8;
+            const int hi = sI[(cy + 1) * RX + cx + 1];
+            const int x = x0 + cx - 1;
+            int si[L::Q];
+            lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+            CT hf[2][L::Q];
+            double h0, h1;
+            gather2d<P, NS, RX, RY>(a, hi, si, BND && x == 0, BND && x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
             sX[0][cy][cx] = h0;
             sX[1][cy][cx] = h1;
         }
-    }
-    // remaining halo entries (a tile that wraps onto itself in y, or one part of a split tile)
-    for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
-        const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
-        const int cx = pw & 255u, cy = pw >> 8;
-        const int hi = sI[(cy + 1) * RX + cx + 1];
-        const int x = x0 + cx - 1;
-        int si[L::Q];
-        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
-        CT hf[2][L::Q];
-        double h0, h1;
-        gather2d<P, NS, RX, RY>(a, hi, si, x == 0, x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
-        sX[0][cy][cx] = h0;
-        sX[1][cy][cx] = h1;
-    }
-    if (io >= 0) {
-        sX[0][cyo][cxo] = X0;
-        sX[1][cyo][cxo] = X1;
-    }
-    __syncthreads();
+        if (io >= 0) {
+            sX[0][cyo][cxo] = X0;
+            sX[1][cyo][cxo] = X1;
+        }
+        __syncthreads();
 
-    if (io < 0) return;
-    const int cx = cxo, cy = cyo;
-    double g0[3], g1[3];
-    const bool xp = nbo & NB_XP, xm = nbo & NB_XM, yp = nbo & NB_YP, ym = nbo & NB_YM;
-    g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
-    g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
-    g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
-    g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
-    g0[2] = g1[2] = 0.0;
-    double om0, om1;
-    bool hit;
-    ms_relax<2>(a, X0, X1, g0, g1, x0 + cx - 1 == a.nx - 1, om0, om1, hit);
-    if (hit) gstore<unsigned>(a.flags, 0u, 1u);
-    collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1);
+        if (io < 0) return;
+        const int cx = cxo, cy = cyo;
+        double g0[3], g1[3];
+        const bool xp = nbo & NB_XP, xm = nbo & NB_XM, yp = nbo & NB_YP, ym = nbo & NB_YM;
+        g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
+        g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
+        g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
+        g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
+        g0[2] = g1[2] = 0.0;
+        double om0, om1;
+        bool hit;
+        ms_relax<2>(a, X0, X1, g0, g1, BND && x0 + cx - 1 == a.nx - 1, om0, om1, hit);
+        if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+        collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1);
+    };
+    if (edge)
+        rest(std::true_type{});
+    else
+        rest(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------------------------
