@@ -246,6 +246,27 @@ def test_reduced_precision_short_run(precision, shift, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("precision,shift,tol", [
+    ("fp32", lbm_ms.SHIFT_GLOBAL, 2e-6),
+    ("fp32", lbm_ms.SHIFT_NODE, 2e-6),
+    ("bf16", lbm_ms.SHIFT_GLOBAL, 2e-3),
+    ("fp16", lbm_ms.SHIFT_NODE, 2e-4),
+    ("bf16", lbm_ms.SHIFT_NODE, 2e-3),
+])
+def test_reduced_precision_short_run_3d(precision, shift, tol):
+    """D3Q19 storage modes against the FP64 oracle (same bounds as the 2D run), on a block that
+    spans several tiles in x and y, two z chunks and ragged tails, with both x faces open."""
+    case = inputs.random_small(70, 11, 37, "D3Q19", seed=12, solid_frac=0.2, tau_ref=4.0)
+    s, o = _pair(case, precision=precision, shift_mode=shift, ms_mode=lbm_ms.STOICH)
+    s.init()
+    o.init_uniform()
+    s.step(100)
+    o.step(100)
+    err = np.max(np.abs(s.get_fields() - o.moments()))
+    print("3D precision %s shift %d: max |dX| after 100 steps = %.3e" % (precision, shift, err))
+    assert err <= tol
+
+
 def test_full_size_porous_2d_fp64_and_fp32():
     """The 1024^2 porous slice in the benchmark's launch shape: a few steps against the oracle."""
     case = inputs.porous_2d()  # 1024 x 1024, seed 2
