@@ -223,6 +223,24 @@ struct RefLds {
     }
 };
 
+// LDS-staged references of a ring of NPL planes ([plane slot][species][RY * RX]); the node sits
+// at column cx, row cy of relative plane zr (slot (zr + 2) % NPL).
+template <int RX, int RY, int NPL>
+struct RefLds3 {
+    const double* sc;
+    int zr, pos;
+    __device__ inline double own(int s, int) const
+    {
+        return sc[((((zr + 2) % NPL + NPL) % NPL) * 2 + s) * RY * RX + pos];
+    }
+    template <class L>
+    __device__ inline double src(int s, int k, unsigned) const
+    {
+        const int slot = ((zr - L::ez[k] + 2) % NPL + NPL) % NPL;
+        return sc[(slot * 2 + s) * RY * RX + pos - L::ey[k] * RX - L::ex[k]];
+    }
+};
+
 template <class L, int P, class REF>
 __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
                                  bool outlet, float (&g)[2][L::Q], double& X0, double& X1,

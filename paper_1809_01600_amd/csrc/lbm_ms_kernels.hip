@@ -218,6 +218,38 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
         rest(std::false_type{});
 }
 
+// stage_plane for plane z plus, for the NODE shift, the FP64 references of its fluid nodes into
+// the matching slot of the reference ring ([species][RY * RX] per slot).
+template <int RX, int RY>
+__device__ inline void stage_plane_refs3d(const StepArgs& a, int x0, int y0, int z, int* dst,
+                                          double* sc)
+{
+    const long long zb = (long long)((z % a.nz + a.nz) % a.nz) * a.nx * a.ny;
+    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
+        const int rx = t % RX, ry = t / RX;
+        const int gx = x0 - 2 + rx;
+        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int i = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
+        dst[t] = i;
+        sc[t] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
+        sc[RX * RY + t] = i >= 0 ? gload<double>(a.xin, (unsigned)(a.NF + i) * 8u) : 0.0;
+    }
+}
+
+// Pull of one node of a 3D tile: NODE-shift references from the staged ring, else the plain
+// gather.  (cx, cy): the node's position in the staged plane, zr its relative plane.
+template <int P, bool NS, int RX, int RY, int NPL>
+__device__ inline void gather3d(const StepArgs& a, int i, const int (&si)[D3Q19::Q], bool inlet,
+                                bool outlet, typename Codec<P>::CT (&f)[2][D3Q19::Q], double& X0,
+                                double& X1, const double* sc, int zr, int cx, int cy)
+{
+    if constexpr (NS)
+        gather_ns<D3Q19, P>(a, i, si, inlet, outlet, f, X0, X1,
+                            RefLds3<RX, RY, NPL>{sc, zr, cy * RX + cx});
+    else
+        gather<D3Q19, P, false>(a, i, si, inlet, outlet, f, X0, X1);
+}
+
 // ---------------------------------------------------------------------------------------------
 // 3D (D3Q19): one workgroup = 64 x TY column tile marching through CZ planes.  The index map is
 // staged in a 5-plane LDS ring one plane ahead; x/y gradients come from a 3-slot LDS ring of
@@ -234,6 +266,7 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
     constexpr int HWAVES = (NHALO + 63) / 64;
     __shared__ int sI[NPL * RY * RX];
     __shared__ double sX[3][2][TY + 2][TX + 2];
+    __shared__ double sC[NS ? NPL * 2 * RY * RX : 1];  // NODE shift: staged reference ring
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = tile % a.tiles_x;
@@ -250,10 +283,17 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
     halo_pos<TX, TY>(threadIdx.x, hx, hy);
     const int hgx = x0 + hx;
     const bool hjob = threadIdx.x < NHALO && hgx >= 0 && hgx < a.nx;
+    auto stage = [&](int zrel) {  // plane z0 + zrel into ring slot (zrel + 2) % NPL
+        const int slot = (zrel + 2) % NPL;
+        if constexpr (NS)
+            stage_plane_refs3d<RX, RY>(a, x0, y0, z0 + zrel, sI + slot * RY * RX, sC + slot * 2 * RY * RX);
+        else
+            stage_plane<RX, RY>(a, x0, y0, z0 + zrel, sI + slot * RY * RX);
+    };
 
     // planes z0-2 .. z0+2 (relative -2 .. 2) into the ring
     for (int zr = -2; zr <= 2; ++zr)
-        stage_plane<RX, RY>(a, x0, y0, z0 + zr, sI + ((zr + 2) % NPL) * RY * RX);
+        stage(zr);
     __syncthreads();
 
     // plane z0-1: moments only (z gradient of plane z0); plane z0: populations and moments
@@ -266,11 +306,13 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
         int si[L::Q];
         lds_sources<L, RX, RY, NPL>(sI, -1, lx + 2, ly + 2, x, a.nx, in_x ? im : -1, si);
         CT tf[2][L::Q];
-        gather<L, P, NS>(a, (in_x && im >= 0) ? im : 0, si, x == 0, x == a.nx - 1, tf, Xm0, Xm1);
+        gather3d<P, NS, RX, RY, NPL>(a, (in_x && im >= 0) ? im : 0, si, x == 0, x == a.nx - 1, tf, Xm0, Xm1,
+                                     sC, -1, lx + 2, ly + 2);
         if (!(in_x && im >= 0)) Xm0 = Xm1 = 0.0;
         ic = in_x ? sI[((2) * RY + ly + 2) * RX + lx + 2] : -1;
         nbc = lds_sources<L, RX, RY, NPL>(sI, 0, lx + 2, ly + 2, x, a.nx, ic, si);
-        gather<L, P, NS>(a, ic < 0 ? 0 : ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1);
+        gather3d<P, NS, RX, RY, NPL>(a, ic < 0 ? 0 : ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1, sC, 0,
+                                     lx + 2, ly + 2);
         if (ic < 0) Xc0 = Xc1 = 0.0;
         double h0 = 0.0, h1 = 0.0;
         if (threadIdx.x < HWAVES * 64) {
@@ -278,7 +320,8 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
             int hsi[L::Q];
             lds_sources<L, RX, RY, NPL>(sI, 0, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
             CT hf[2][L::Q];
-            gather<L, P, NS>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+            gather3d<P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1,
+                                         hf, h0, h1, sC, 0, hx + 2, hy + 2);
             if (hi < 0) h0 = h1 = 0.0;
         }
         sX[0][0][ly + 1][lx + 1] = Xc0;
@@ -294,7 +337,7 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
         const int zi = z0 + it;
         if (zi >= a.nz) break;  // uniform across the workgroup
         // stage plane it+3 (read by the next iteration's pull)
-        stage_plane<RX, RY>(a, x0, y0, z0 + it + 3, sI + ((it + 5) % NPL) * RY * RX);
+        stage(it + 3);
         // pull plane it+1: own column (populations kept) and, if the next plane is output, its halo
         const int zr = it + 1;
         const int pslot = (zr + 2) % NPL;
@@ -303,7 +346,8 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
         const uint32_t nbn = lds_sources<L, RX, RY, NPL>(sI, zr, lx + 2, ly + 2, x, a.nx, in_, si);
         CT fn[2][L::Q];
         double Xp0, Xp1;
-        gather<L, P, NS>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1);
+        gather3d<P, NS, RX, RY, NPL>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1, sC, zr,
+                                     lx + 2, ly + 2);
         if (in_ < 0) Xp0 = Xp1 = 0.0;
         const bool need_next = (it + 1 < CZ) && (zi + 1 < a.nz);
         const int s_next = (it + 1) % 3;
@@ -314,7 +358,8 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
                 int hsi[L::Q];
                 lds_sources<L, RX, RY, NPL>(sI, zr, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
                 CT hf[2][L::Q];
-                gather<L, P, NS>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+                gather3d<P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0,
+                                             hjob && hgx == a.nx - 1, hf, h0, h1, sC, zr, hx + 2, hy + 2);
                 if (hi < 0) h0 = h1 = 0.0;
             }
             sX[s_next][0][ly + 1][lx + 1] = Xp0;
