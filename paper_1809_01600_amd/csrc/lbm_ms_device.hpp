@@ -33,6 +33,15 @@ struct D2Q9 {
     static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
     static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    // FP32 weights whose exact sum is one (the nearest floats to 4/9, 1/9, 1/36 sum to 1 + 7.5e-9,
+    // and a collision toward w_a X in float would then create that fraction of X at every node off
+    // equilibrium, a bias in the steady state): 1/9 and 1/36 in units of 2^-27, the rest weight
+    // the remainder in units of 2^-25, each within 6e-8 of its weight
+    static constexpr long long M1 = ((1LL << 27) + 4) / 9, M2 = ((1LL << 27) + 18) / 36;
+    static constexpr float W0F = (float)((double)((1LL << 25) - M1 - M2) / (double)(1LL << 25));
+    static constexpr float W1F = (float)((double)M1 / (double)(1LL << 27));
+    static constexpr float W2F = (float)((double)M2 / (double)(1LL << 27));
+    static constexpr float wf[9] = {W0F, W1F, W1F, W1F, W1F, W2F, W2F, W2F, W2F};
 };
 
 // D3Q19 with opposite links adjacent: rest, +-x, +-y, +-z, then the twelve edge vectors.
@@ -47,10 +56,44 @@ struct D3Q19 {
                                      1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    // FP32 weights whose exact sum is one (the nearest floats sum to 1 + 1.5e-8): 1/18 in units of
+    // 2^-28, 1/36 in units of 2^-29 taken at the next value below it with M1 + M2 divisible by 4,
+    // so that the remainder 1 - 6 w1 - 12 w2, the rest weight, is a float; each within 1.3e-7 of
+    // its weight
+    static constexpr long long M1 = ((1LL << 28) + 9) / 18, R2 = ((1LL << 29) + 18) / 36;
+    static constexpr long long M2 = R2 - (M1 + R2) % 4;
+    static constexpr float W0F = (float)((double)((1LL << 28) - 6 * M1 - 6 * M2) / (double)(1LL << 28));
+    static constexpr float W1F = (float)((double)M1 / (double)(1LL << 28));
+    static constexpr float W2F = (float)((double)M2 / (double)(1LL << 29));
+    static constexpr float wf[19] = {W0F, W1F, W1F, W1F, W1F, W1F, W1F, W2F, W2F, W2F,
+                                     W2F, W2F, W2F, W2F, W2F, W2F, W2F, W2F, W2F};
 };
 
 // sum of the weights of the links with e_x = +1 (1/6 for both sets)
 constexpr double W_OUT = 1.0 / 6.0;
+
+// Sum of a float weight table in FP64 (exact: every entry is a multiple of 2^-29 below one) and
+// the check that the rest weight survived its cast to float.
+template <class L>
+constexpr double wf_sum()
+{
+    double t = 0.0;
+    for (int k = 0; k < L::Q; ++k) t += (double)L::wf[k];
+    return t;
+}
+static_assert(wf_sum<D2Q9>() == 1.0 && wf_sum<D3Q19>() == 1.0, "float weights must sum to one");
+static_assert((double)D2Q9::W0F * (1LL << 25) == (double)((1LL << 25) - D2Q9::M1 - D2Q9::M2),
+              "D2Q9 rest weight is not a float");
+static_assert((double)D3Q19::W0F * (1LL << 28) == (double)((1LL << 28) - 6 * D3Q19::M1 - 6 * D3Q19::M2),
+              "D3Q19 rest weight is not a float");
+
+// Weight of link k in the arithmetic type CT: the FP64 weights, or the float table above.
+template <class L, class CT>
+__host__ __device__ constexpr CT wgt(int k)
+{
+    if constexpr (sizeof(CT) == sizeof(double)) return (CT)L::w[k];
+    else return L::wf[k];
+}
 
 // ---------------------------------------------------------------------------------------------
 // population storage
@@ -295,16 +338,16 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
     AT S0 = 0, S1 = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        S0 += (AT)((float)L::w[k] * dc[0][k]) + (AT)g[0][k];
-        S1 += (AT)((float)L::w[k] * dc[1][k]) + (AT)g[1][k];
+        S0 += (AT)(L::wf[k] * dc[0][k]) + (AT)g[0][k];
+        S1 += (AT)(L::wf[k] * dc[1][k]) + (AT)g[1][k];
     }
     X0 = co0 + (double)S0;
     X1 = co1 + (double)S1;
     const float s0 = (float)S0, s1 = (float)S1;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        g[0][k] += (float)L::w[k] * (dc[0][k] - s0);
-        g[1][k] += (float)L::w[k] * (dc[1][k] - s1);
+        g[0][k] += L::wf[k] * (dc[0][k] - s0);
+        g[1][k] += L::wf[k] * (dc[1][k] - s1);
     }
 }
 
@@ -339,7 +382,7 @@ __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], b
         const raw r0 = gload<raw>(fin, off);
         const raw r1 = gload<raw>(fin, off + spec);
         if constexpr (C::shifted) {
-            const float wk = (float)L::w[k];  // w of the opposite link is the same
+            const float wk = L::wf[k];  // w of the opposite link is the same
             f[0][k] = C::dec(r0, wk * cg0);
             f[1][k] = C::dec(r1, wk * cg1);
         } else {
@@ -502,12 +545,12 @@ __device__ inline void collide_store(const StepArgs& a, int n,
     const float c0 = (float)a.c0, c1 = (float)a.c1;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        const CT wk = (CT)L::w[k];
+        const CT wk = wgt<L, CT>(k);
         const CT v0 = f[0][k] + o0 * (wk * x0 - f[0][k]);
         const CT v1 = f[1][k] + o1 * (wk * x1 - f[1][k]);
         const unsigned off = base + (unsigned)k * plane;
         if constexpr (C::shifted) {
-            const float wf = (float)L::w[k];
+            const float wf = L::wf[k];
             gstore<raw>(fout, off, C::enc(v0, wf * c0));
             gstore<raw>(fout, off + spec, C::enc(v1, wf * c1));
         } else {

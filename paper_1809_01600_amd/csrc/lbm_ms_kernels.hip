@@ -430,9 +430,11 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
         }
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
-            const CT e0 = (CT)(L::w[k] * v0), e1 = (CT)(L::w[k] * v1);
+            // the equilibrium w_a X in the arithmetic of the collision, so that a uniform start
+            // is its fixed point
+            const CT e0 = wgt<L, CT>(k) * (CT)v0, e1 = wgt<L, CT>(k) * (CT)v1;
             if constexpr (C::shifted) {
-                const float wf = (float)L::w[k];
+                const float wf = L::wf[k];
                 fout[(long long)k * a.P + i] = C::enc(e0, wf * c0);
                 fout[(long long)(L::Q + k) * a.P + i] = C::enc(e1, wf * c1);
             } else {
@@ -462,7 +464,7 @@ __device__ inline void node_moments(const StepArgs& a, int i, double& X0, double
             s0 += (double)C::dec(fin[(long long)k * a.P + i], 0.f);
             s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], 0.f);
         } else if constexpr (C::shifted) {
-            const float wf = (float)L::w[k];
+            const float wf = L::wf[k];
             s0 += (double)C::dec(fin[(long long)k * a.P + i], wf * c0);
             s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], wf * c1);
         } else {
@@ -571,17 +573,17 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                 // post-stream population (NODE shift: f = w X + g)
                 double p0 = (double)f[0][q], p1 = (double)f[1][q];
                 if constexpr (NS) {
-                    p0 += L::w[q] * X0;
-                    p1 += L::w[q] * X1;
+                    p0 += (double)L::wf[q] * X0;
+                    p1 += (double)L::wf[q] * X1;
                 }
                 // post-collision population of this node leaving through the face
                 double o0, o1;
                 if constexpr (NS) {
-                    o0 = L::w[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
-                    o1 = L::w[q] * a.xin[a.NF + i] +
+                    o0 = (double)L::wf[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
+                    o1 = (double)L::wf[q] * a.xin[a.NF + i] +
                          (double)C::dec(fin[(long long)(L::Q + q) * a.P + i], 0.f);
                 } else if constexpr (C::shifted) {
-                    const float wf = (float)L::w[q];
+                    const float wf = L::wf[q];
                     o0 = C::dec(fin[(long long)q * a.P + i], wf * c0);
                     o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], wf * c1);
                 } else {
@@ -647,8 +649,8 @@ __global__ void k_populations(StepArgs a, int s, int q, double* out)
         if (i >= 0) {
             const float c = (float)(s ? a.c1 : a.c0);
             const raw r = fin[((long long)s * L::Q + q) * a.P + i];
-            if constexpr (NS) v = L::w[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
-            else if constexpr (C::shifted) v = C::dec(r, (float)L::w[q] * c);
+            if constexpr (NS) v = (double)L::wf[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
+            else if constexpr (C::shifted) v = C::dec(r, L::wf[q] * c);
             else v = C::dec(r, 0);
         }
         out[n] = v;

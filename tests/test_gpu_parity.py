@@ -315,3 +315,80 @@ def test_node_shift_steady_state_matches_fp64(precision, x_tol, eta_tol):
     assert dX <= x_tol and deta <= eta_tol
     s.close()
     ref.close()
+
+
+
+def _conservation_tol(precision, q, n_fluid, inv):
+    """Bound on |change of inventory - (inflow - outflow)| over one step from rounding alone.
+    FP64: two tree reductions of the inventory, each within ~log2(N) eps of it.  FP32 storage: each
+    of the q n_fluid stored values (deviations from the reference, below 1/3 in size) is rounded
+    once per step to half an ulp, at most 2^-26; the rounding errors are taken as independent, so
+    their sum stays within 8 standard deviations of sqrt(q n_fluid) 2^-26 / sqrt(3)."""
+    if precision == "fp64":
+        return 2.0 * np.log2(n_fluid) * 2.0 ** -52 * inv
+    return np.full(2, 8.0 * np.sqrt(q * n_fluid) * 2.0 ** -26 / np.sqrt(3.0))
+
+
+def _outflow_tol(precision, info):
+    """Bound on |outflow - Q_s n_open| from rounding: the populations that cross an outlet node's
+    face sum in size to at most 1/3 (their weights sum to 1/6 in either direction, X <= 1); FP32
+    storage and arithmetic move that sum by at most a few ulps, taken as 4 ulps of 1/3 per node."""
+    scale = np.abs(np.array(info.Q[:2])) * info.n_open_outlet
+    if precision == "fp64":
+        return 1e-9 * scale
+    return np.full(2, 4.0 * 2.0 ** -24 / 3.0 * info.n_open_outlet)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_porous_3d_conserves_species(precision):
+    """The 256^3 porous block in the benchmark's launch configuration: one step changes each
+    species' inventory by the inlet inflow minus the outlet outflow, to rounding (the oracle cannot
+    step this size within a test; conservation holds at any size), and the outflow is the imposed
+    flux Q_s on every open outlet node."""
+    case = inputs.porous_3d()  # 256^3, seed 3
+    s = lbm_ms.Solver(case, precision=precision)
+    info = s.get_info()
+    # a random start, so that the inlet face carries a nonzero inflow from the first step
+    s.init(inputs.random_field(case.shape, seed=21, lo=0.2, hi=0.8))
+    s.step(5)
+    for _ in range(2):
+        inv, inflow, outflow = s.mass_balance()
+        s.step(1)
+        inv2, _, _ = s.mass_balance()
+        dout = np.abs(outflow - np.array(info.Q[:2]) * info.n_open_outlet)
+        err = np.abs((inv2 - inv) - (inflow - outflow))
+        tol = _conservation_tol(precision, 19, info.n_fluid, inv)
+        print("256^3 %s: inventory %s, in %s, out %s, |out - Q n_open| %s (bound %s), "
+              "|error| %s (bound %s)" % (precision, inv, inflow, outflow, dout,
+                                         _outflow_tol(precision, info), err, tol), flush=True)
+        assert np.all(dout <= _outflow_tol(precision, info))
+        assert np.all(err <= tol)
+    s.close()
+
+
+def test_full_size_batch_conserves_species_per_instance():
+    """The 64-slice batch of the benchmark (sides 256..1024, FP32) advanced by batched steps from a
+    random start: for the smallest, a middle and the largest instance, one step changes the
+    inventory by the inflow minus the imposed outflow, to rounding."""
+    cases = inputs.batch_2d(tau_ref=3.0, accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+    b = lbm_ms.Batch(cases, precision="fp32")
+    b.init(np.concatenate([inputs.random_field(c.shape, seed=22 + k, lo=0.2, hi=0.8).reshape(-1)
+                           for k, c in enumerate(cases)]))
+    b.step(5)
+    sides = [c.nx for c in cases]
+    picks = sorted({int(np.argmin(sides)), len(cases) // 2, int(np.argmax(sides))})
+    before = {k: b.instance(k).mass_balance() for k in picks}
+    b.step(1)
+    for k in picks:
+        inv, inflow, outflow = before[k]
+        inv2, _, _ = b.instance(k).mass_balance()
+        info = b.instance(k).get_info()
+        dout = np.abs(outflow - np.array(info.Q[:2]) * info.n_open_outlet)
+        err = np.abs((inv2 - inv) - (inflow - outflow))
+        tol = _conservation_tol("fp32", 9, info.n_fluid, inv)
+        print("batch instance %d (side %d): in %s, out %s, |out - Q n_open| %s (bound %s), "
+              "|error| %s (bound %s)" % (k, sides[k], inflow, outflow, dout,
+                                         _outflow_tol("fp32", info), err, tol), flush=True)
+        assert np.all(dout <= _outflow_tol("fp32", info)), k
+        assert np.all(err <= tol), k
+    b.close()
