@@ -333,21 +333,23 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
         }
     }
     // the sum of small terms: FP64 for FP32 deviations; FP32 for 16-bit ones, whose own rounding
-    // (about 1e-3 of each term) dwarfs that of an FP32 sum
+    // (about 1e-3 of each term) dwarfs that of an FP32 sum.  The weights here are the nearest
+    // floats, not the unit-sum table: they multiply reference differences and so shape the
+    // diffusion operator, while the FP64 reference already makes the node update conservative.
     using AT = typename std::conditional<P == P_F32, double, float>::type;
     AT S0 = 0, S1 = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        S0 += (AT)(L::wf[k] * dc[0][k]) + (AT)g[0][k];
-        S1 += (AT)(L::wf[k] * dc[1][k]) + (AT)g[1][k];
+        S0 += (AT)((float)L::w[k] * dc[0][k]) + (AT)g[0][k];
+        S1 += (AT)((float)L::w[k] * dc[1][k]) + (AT)g[1][k];
     }
     X0 = co0 + (double)S0;
     X1 = co1 + (double)S1;
     const float s0 = (float)S0, s1 = (float)S1;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        g[0][k] += L::wf[k] * (dc[0][k] - s0);
-        g[1][k] += L::wf[k] * (dc[1][k] - s1);
+        g[0][k] += (float)L::w[k] * (dc[0][k] - s0);
+        g[1][k] += (float)L::w[k] * (dc[1][k] - s1);
     }
 }
 

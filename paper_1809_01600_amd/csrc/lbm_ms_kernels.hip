@@ -573,14 +573,14 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                 // post-stream population (NODE shift: f = w X + g)
                 double p0 = (double)f[0][q], p1 = (double)f[1][q];
                 if constexpr (NS) {
-                    p0 += (double)L::wf[q] * X0;
-                    p1 += (double)L::wf[q] * X1;
+                    p0 += L::w[q] * X0;
+                    p1 += L::w[q] * X1;
                 }
                 // post-collision population of this node leaving through the face
                 double o0, o1;
                 if constexpr (NS) {
-                    o0 = (double)L::wf[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
-                    o1 = (double)L::wf[q] * a.xin[a.NF + i] +
+                    o0 = L::w[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
+                    o1 = L::w[q] * a.xin[a.NF + i] +
                          (double)C::dec(fin[(long long)(L::Q + q) * a.P + i], 0.f);
                 } else if constexpr (C::shifted) {
                     const float wf = L::wf[q];
@@ -649,7 +649,7 @@ __global__ void k_populations(StepArgs a, int s, int q, double* out)
         if (i >= 0) {
             const float c = (float)(s ? a.c1 : a.c0);
             const raw r = fin[((long long)s * L::Q + q) * a.P + i];
-            if constexpr (NS) v = (double)L::wf[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
+            if constexpr (NS) v = L::w[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
             else if constexpr (C::shifted) v = C::dec(r, L::wf[q] * c);
             else v = C::dec(r, 0);
         }
