@@ -353,23 +353,19 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
     }
 }
 
-template <class L, int P, bool NS>
-__device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
-                              bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
-                              double& X1)
+// The plain gather in two halves, so that a caller can issue the loads of several nodes before
+// it waits for any of them: gather_issue loads the raw stored values each link pulls (the source
+// entry, or this node's own opposite entry where it reflects), gather_finish decodes them,
+// applies the outlet flux share and the inlet rule (Eq. 36), and sums the moments.
+template <class L, int P>
+__device__ inline void gather_issue(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                                    bool outlet, typename Codec<P>::raw (&r)[2][L::Q])
 {
-    if constexpr (NS) {
-        gather_ns<L, P>(a, i, si, inlet, outlet, f, X0, X1, RefGlobal{a.xin, (unsigned)a.NF * 8u});
-        return;
-    }
-    using C = Codec<P>;
-    using CT = typename C::CT;
-    using raw = typename C::raw;
+    using raw = typename Codec<P>::raw;
     constexpr unsigned ES = sizeof(raw);
     const void* fin = a.fin;
     const unsigned plane = (unsigned)a.P * ES;          // bytes per (species, link) plane
     const unsigned spec = (unsigned)L::Q * plane;       // bytes per species
-    const float cg0 = (float)a.c0, cg1 = (float)a.c1;
     const bool wall = a.inlet_wall != 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -381,15 +377,30 @@ __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], b
         const bool reflect = (s == -1) || from_out || (from_in && wall);
         const unsigned m = (unsigned)(local ? i : s);
         const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + m * ES;
-        const raw r0 = gload<raw>(fin, off);
-        const raw r1 = gload<raw>(fin, off + spec);
+        r[0][k] = gload<raw>(fin, off);
+        r[1][k] = gload<raw>(fin, off + spec);
+    }
+}
+
+template <class L, int P>
+__device__ inline void gather_finish(const StepArgs& a, const typename Codec<P>::raw (&r)[2][L::Q],
+                                     bool inlet, bool outlet, typename Codec<P>::CT (&f)[2][L::Q],
+                                     double& X0, double& X1)
+{
+    using C = Codec<P>;
+    using CT = typename C::CT;
+    const float cg0 = (float)a.c0, cg1 = (float)a.c1;
+    const bool wall = a.inlet_wall != 0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const bool from_out = (L::ex[k] == -1) && outlet;
         if constexpr (C::shifted) {
             const float wk = L::wf[k];  // w of the opposite link is the same
-            f[0][k] = C::dec(r0, wk * cg0);
-            f[1][k] = C::dec(r1, wk * cg1);
+            f[0][k] = C::dec(r[0][k], wk * cg0);
+            f[1][k] = C::dec(r[1][k], wk * cg1);
         } else {
-            f[0][k] = C::dec(r0, CT(0));
-            f[1][k] = C::dec(r1, CT(0));
+            f[0][k] = C::dec(r[0][k], CT(0));
+            f[1][k] = C::dec(r[1][k], CT(0));
         }
         if (L::ex[k] == -1) {
             const CT frac = (CT)(L::w[L::opp[k]] / W_OUT);
@@ -414,6 +425,21 @@ __device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], b
     }
     X0 = s0;
     X1 = s1;
+}
+
+template <class L, int P, bool NS>
+__device__ inline void gather(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                              bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
+                              double& X1)
+{
+    if constexpr (NS) {
+        gather_ns<L, P>(a, i, si, inlet, outlet, f, X0, X1, RefGlobal{a.xin, (unsigned)a.NF * 8u});
+        return;
+    } else {
+        typename Codec<P>::raw r[2][L::Q];
+        gather_issue<L, P>(a, i, si, inlet, outlet, r);
+        gather_finish<L, P>(a, r, inlet, outlet, f, X0, X1);
+    }
 }
 
 // Pull of node (x, y, z) (dense n, compact i) through the global index map; returns NB_* bits.

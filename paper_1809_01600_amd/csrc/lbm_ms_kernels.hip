@@ -67,6 +67,36 @@ __device__ inline void stage_plane(const StepArgs& a, int x0, int y0, int z, int
     }
 }
 
+// stage_plane in two halves for a caller that overlaps the index loads with other work: the
+// loads of this thread's share of plane z into registers, then their store into dst (NT threads).
+template <int RX, int RY, int NT>
+struct PlaneRegs {
+    int v[(RX * RY + NT - 1) / NT];
+};
+template <int RX, int RY, int NT>
+__device__ inline void stage_issue(const StepArgs& a, int x0, int y0, int z, PlaneRegs<RX, RY, NT>& r)
+{
+    const long long zb = (long long)((z % a.nz + a.nz) % a.nz) * a.nx * a.ny;
+#pragma unroll
+    for (int j = 0; j < (RX * RY + NT - 1) / NT; ++j) {
+        const int t = threadIdx.x + j * NT;
+        const int rx = t % RX, ry = t / RX;
+        const int gx = x0 - 2 + rx;
+        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        r.v[j] = (t < RX * RY && gx >= 0 && gx < a.nx)
+                     ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
+    }
+}
+template <int RX, int RY, int NT>
+__device__ inline void stage_store(const PlaneRegs<RX, RY, NT>& r, int* dst)
+{
+#pragma unroll
+    for (int j = 0; j < (RX * RY + NT - 1) / NT; ++j) {
+        const int t = threadIdx.x + j * NT;
+        if (t < RX * RY) dst[t] = r.v[j];
+    }
+}
+
 // stage_plane plus, for the NODE shift, the FP64 references c of every staged fluid node
 // (loaded by the same thread right after its index, so one barrier covers both).
 template <int RX, int RY>
@@ -333,35 +363,63 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
     }
     __syncthreads();  // the ring slot of plane z0-2 is free from here on
 
+    // Global-shift storage overlaps the memory round trips of an iteration: the index loads of the
+    // plane staged for later and the population loads of the own column and of the halo are all
+    // issued before any of them is used, and the staged plane is stored to LDS last (its slot is
+    // not read in this iteration, but the compiler cannot tell, so an early store would hold the
+    // pull's LDS reads behind the index loads).  FP64 keeps the halo after the own column: its
+    // registers are already full.
+    constexpr bool OVERLAP = !NS;
+    constexpr bool MERGE_HALO = !NS && P != P_F64;
+    using raw = typename Codec<P>::raw;
     for (int it = 0; it < CZ; ++it) {
         const int zi = z0 + it;
         if (zi >= a.nz) break;  // uniform across the workgroup
         // stage plane it+3 (read by the next iteration's pull)
-        stage(it + 3);
+        PlaneRegs<RX, RY, 64 * TY> stg;
+        if constexpr (OVERLAP)
+            stage_issue<RX, RY, 64 * TY>(a, x0, y0, z0 + it + 3, stg);
+        else
+            stage(it + 3);
         // pull plane it+1: own column (populations kept) and, if the next plane is output, its halo
         const int zr = it + 1;
         const int pslot = (zr + 2) % NPL;
         const int in_ = in_x ? sI[(pslot * RY + ly + 2) * RX + lx + 2] : -1;
         int si[L::Q];
         const uint32_t nbn = lds_sources<L, RX, RY, NPL>(sI, zr, lx + 2, ly + 2, x, a.nx, in_, si);
-        CT fn[2][L::Q];
-        double Xp0, Xp1;
-        gather3d<P, NS, RX, RY, NPL>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1, sC, zr,
-                                     lx + 2, ly + 2);
-        if (in_ < 0) Xp0 = Xp1 = 0.0;
         const bool need_next = (it + 1 < CZ) && (zi + 1 < a.nz);
-        const int s_next = (it + 1) % 3;
-        if (need_next) {
-            double h0 = 0.0, h1 = 0.0;
-            if (threadIdx.x < HWAVES * 64) {
-                const int hi = hjob ? sI[(pslot * RY + hy + 2) * RX + hx + 2] : -1;
+        const bool hwave = need_next && threadIdx.x < HWAVES * 64;  // uniform per wave
+        const int hi = (hwave && hjob) ? sI[(pslot * RY + hy + 2) * RX + hx + 2] : -1;
+        CT fn[2][L::Q];
+        double Xp0, Xp1, h0 = 0.0, h1 = 0.0;
+        if constexpr (MERGE_HALO) {
+            raw rn[2][L::Q], rh[2][L::Q];
+            gather_issue<L, P>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, rn);
+            if (hwave) {
+                int hsi[L::Q];
+                lds_sources<L, RX, RY, NPL>(sI, zr, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
+                gather_issue<L, P>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, rh);
+            }
+            gather_finish<L, P>(a, rn, x == 0, x == a.nx - 1, fn, Xp0, Xp1);
+            if (hwave) {
+                CT hf[2][L::Q];
+                gather_finish<L, P>(a, rh, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+            }
+        } else {
+            gather3d<P, NS, RX, RY, NPL>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1, sC,
+                                         zr, lx + 2, ly + 2);
+            if (hwave) {
                 int hsi[L::Q];
                 lds_sources<L, RX, RY, NPL>(sI, zr, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
                 CT hf[2][L::Q];
                 gather3d<P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0,
                                              hjob && hgx == a.nx - 1, hf, h0, h1, sC, zr, hx + 2, hy + 2);
-                if (hi < 0) h0 = h1 = 0.0;
             }
+        }
+        if (in_ < 0) Xp0 = Xp1 = 0.0;
+        if (hi < 0) h0 = h1 = 0.0;
+        const int s_next = (it + 1) % 3;
+        if (need_next) {
             sX[s_next][0][ly + 1][lx + 1] = Xp0;
             sX[s_next][1][ly + 1][lx + 1] = Xp1;
             if (threadIdx.x < NHALO) {
@@ -369,6 +427,7 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
                 sX[s_next][1][hy + 1][hx + 1] = h1;
             }
         }
+        if constexpr (OVERLAP) stage_store<RX, RY, 64 * TY>(stg, sI + (it + 5) % NPL * RY * RX);
         __syncthreads();
         if (own && ic >= 0) {
             const int s = it % 3;

@@ -400,11 +400,9 @@ int default_tile_y(const lbm_ms_params& p)
 {
     if (p.tile_y > 0) return p.tile_y;
     if (p.lattice == LBM_MS_D2Q9) return p.ny >= 8 ? 8 : 4;
-    // measured on a 256^3 porous block: FP64 and 16-bit global-shift storage run best with the
-    // 256-lane tiles, FP32 and NODE-shift storage with the 512-lane ones
-    const bool narrow = p.precision == LBM_MS_FP64 ||
-                        ((p.precision == LBM_MS_FP16 || p.precision == LBM_MS_BF16) && !node_shift(p));
-    return narrow ? 4 : 8;
+    // measured on a 256^3 porous block: FP64 runs best with the 256-lane tiles (its 512-lane
+    // build spills), every other storage mode with the 512-lane ones
+    return p.precision == LBM_MS_FP64 ? 4 : 8;
 }
 
 int default_chunk_z(const lbm_ms_params& p)
