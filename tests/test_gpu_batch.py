@@ -52,7 +52,7 @@ def test_batch_fp64_matches_oracle():
     b.init()
     b.step(150)
     for k, c in enumerate(cases):
-        o = oracle.Oracle(c, eps=b.instance(k).get_info().eps_flux)
+        o = oracle.Oracle(c)
         o.init_uniform()
         o.step(150)
         assert np.max(np.abs(b.instance(k).get_fields() - o.moments())) < 1e-12

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_windows as ow
 from paper_1809_01600_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -33,8 +34,9 @@ def _percolating_2d(n, ny, seed0=0, **kw):
 def _pair(case, precision="fp64", ms_mode=lbm_ms.LOCAL_FLUX, inlet_wall=False, **kw):
     s = lbm_ms.Solver(case, precision=precision, ms_mode=ms_mode,
                       inlet_mode=lbm_ms.INLET_WALL if inlet_wall else lbm_ms.INLET_DIRICHLET, **kw)
-    info = s.get_info()
-    o = oracle.Oracle(case, ms_mode=ms_mode, inlet_wall=inlet_wall, eps=info.eps_flux)
+    # the oracle derives its own regularizer unless the test sets one for both sides
+    eps = kw.get("eps_flux", -1.0)
+    o = oracle.Oracle(case, ms_mode=ms_mode, inlet_wall=inlet_wall, eps=eps if eps > 0 else None)
     return s, o
 
 
@@ -316,6 +318,55 @@ def test_node_shift_steady_state_matches_fp64(precision, x_tol, eta_tol):
     s.close()
     ref.close()
 
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", 3e-6)])
+def test_full_size_porous_3d_sampled_columns(precision, tol):
+    """The 256^3 porous block in the benchmark's launch shape (default tile), two steps from a
+    random start, element by element on sampled x-columns against the oracle stepped on windows
+    that reproduce those columns exactly (tests/oracle_windows.py; the whole block is beyond
+    the oracle's reach in a test).  Half the columns are open at both the inlet and the outlet."""
+    case = inputs.porous_3d()  # 256^3, seed 3
+    X0 = inputs.random_field(case.shape, seed=9, lo=0.2, hi=0.8)
+    mask, Q, eps = ow.full_inputs(case)
+    rng = np.random.Generator(np.random.PCG64(12))
+    open_ends = np.argwhere((mask[:, :, 0] == 0) & (mask[:, :, -1] == 0))  # (z, y)
+    pick = open_ends[rng.choice(len(open_ends), 6, replace=False)]
+    columns = [(int(y), int(z)) for z, y in pick]
+    columns += [(int(rng.integers(case.ny)), int(rng.integers(case.nz))) for _ in range(6)]
+    rows = ow.column_rows(case, X0, 2, columns, mask, Q, eps)
+    s = lbm_ms.Solver(case, precision=precision)
+    info = s.get_info()
+    assert np.array_equal(s.get_geometry(), mask)
+    assert np.allclose(np.array(info.Q[:2]), Q, rtol=1e-15, atol=0)
+    s.init(X0)
+    s.step(2)
+    X = s.get_fields()
+    err = max(float(np.max(np.abs(X[:, z, y, :] - row))) for (y, z), row in zip(columns, rows))
+    print("256^3 %s tile (%d, %d): max |dX| on %d sampled columns after 2 steps = %.3e"
+          % (precision, info.tile_y, info.chunk_z, len(columns), err))
+    assert err <= tol
+    s.close()
+
+
+def test_full_size_batch_instances_match_oracle():
+    """The benchmark's 64-slice batch (sides 256..1024, FP32, default tile) advanced two steps
+    from a random start in one launch per step: the smallest, a middle and the largest instance
+    against the oracle stepped on that instance alone."""
+    cases = inputs.batch_2d(tau_ref=3.0, accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+    X0 = [inputs.random_field(c.shape, seed=40 + k, lo=0.2, hi=0.8) for k, c in enumerate(cases)]
+    b = lbm_ms.Batch(cases, precision="fp32")
+    b.init(np.concatenate([x.reshape(-1) for x in X0]))
+    b.step(2)
+    sides = [c.nx for c in cases]
+    for k in sorted({int(np.argmin(sides)), len(cases) // 2, int(np.argmax(sides))}):
+        o = oracle.Oracle(cases[k])
+        o.init_field(X0[k])
+        o.step(2)
+        err = float(np.max(np.abs(b.instance(k).get_fields() - o.moments())))
+        print("batch instance %d (side %d): max |dX| after 2 steps = %.3e" % (k, sides[k], err))
+        assert err <= 3e-6, k
+    b.close()
 
 
 def _conservation_tol(precision, q, n_fluid, inv):
