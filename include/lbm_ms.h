@@ -116,7 +116,12 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
 /* Solid mask on the host, nx*ny*nz bytes (1 = solid).  Fluid that no chain of lattice links
  * (periodic in y and z) connects to the inlet column becomes solid; E_GEOM when no fluid node of
  * the outlet column remains.  The fluid index map of the cleaned mask goes to the device.
- * In LBM_MS_INLET_WALL mode the mask is used as given. */
+ * In LBM_MS_INLET_WALL mode the mask is used as given.
+ * Size limit: the kernels address each population buffer (2 species x Q links x P elements of
+ * the storage type, P = fluid nodes rounded up to 64, plus 192) with 32-bit byte offsets, so
+ * E_ARG when it would exceed 4 GiB: about 28.2 M fluid nodes for D3Q19 FP32, 14.1 M for FP64,
+ * 56.5 M for 16-bit storage (D2Q9: 59.6 M, 29.8 M, 119 M); with the NODE shift also at most
+ * 268 M fluid nodes.  lbm_ms_workspace_bytes rejects boxes of more than 2^30 voxels. */
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
 
 /* The same clean-up on the host only (no device, no handle): solid_out = cleaned mask,

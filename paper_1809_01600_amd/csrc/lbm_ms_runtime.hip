@@ -64,7 +64,8 @@ bool valid_params(const lbm_ms_params* p, std::string* why)
     if (p->nx < 2 || p->ny < 1 || p->nz < 1) return fail("need nx >= 2, ny >= 1, nz >= 1");
     if (p->lattice == LBM_MS_D2Q9 && p->nz != 1) return fail("D2Q9 needs nz == 1");
     const long long N = (long long)p->nx * p->ny * p->nz;
-    if (N > (1ll << 31)) return fail("domain too large (more than 2^31 nodes)");
+    // the kernels address the index map with 32-bit byte offsets from its base
+    if (N > (1ll << 30)) return fail("domain too large (more than 2^30 voxels)");
     if (p->precision < LBM_MS_FP64 || p->precision > LBM_MS_BF16) return fail("unknown precision");
     if (p->shift_mode != LBM_MS_SHIFT_GLOBAL && p->shift_mode != LBM_MS_SHIFT_NODE)
         return fail("unknown shift mode");
@@ -567,6 +568,16 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
     std::vector<int32_t> idx;
     h->n_fluid = build_index(h->mask, idx);
     h->P = plane_pitch(h->n_fluid);
+    // the kernels address a population buffer and the NODE-shift references with 32-bit byte
+    // offsets from their bases
+    const unsigned long long fbytes = 2ull * h->q * (unsigned long long)h->P * elem_bytes(h->p.precision);
+    const unsigned long long xbytes = node_shift(h->p) ? 16ull * (unsigned long long)h->n_fluid : 0ull;
+    if (fbytes > (1ull << 32) || xbytes > (1ull << 32)) {
+        h->geom = false;
+        return h->fail(LBM_MS_E_ARG,
+                       "%lld fluid nodes: one population buffer would take %llu bytes, beyond the "
+                       "4 GiB that 32-bit offsets address", h->n_fluid, fbytes);
+    }
     int rc = h->hip(hipMemcpyAsync(h->at(h->L.idx), idx.data(), idx.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, h->stream), "index upload");
     if (rc) return rc;

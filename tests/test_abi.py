@@ -99,3 +99,12 @@ def test_host_clean_up_matches_oracle_labelling(lat, shape, frac, seed):
     ref, n_ref = oracle.label(lat, solid)
     assert np.array_equal(got, ref)
     assert n_open == n_ref
+
+
+def test_box_size_limit_of_the_index_offsets():
+    """The index map is addressed with 32-bit byte offsets: 2^30 voxels are accepted, one more
+    plane is rejected (the workspace size query returns 0 for invalid parameters)."""
+    ok = inputs.Case(name="big", lattice="D3Q19", nx=1024, ny=1024, nz=1024)
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(lbm_ms.make_params(ok, precision=lbm_ms.FP32))) > 0
+    big = inputs.Case(name="too big", lattice="D3Q19", nx=1024, ny=1024, nz=1025)
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(lbm_ms.make_params(big, precision=lbm_ms.FP32))) == 0

@@ -369,6 +369,30 @@ def test_full_size_batch_instances_match_oracle():
     b.close()
 
 
+def test_population_buffer_size_limit_fp64_3d():
+    """Largest sizes: an all-fluid FP64 D3Q19 box of 241^3 (14.0 M fluid nodes) puts the last
+    population of a buffer about 4.26 GB from its base, just inside the 32-bit offsets; one step
+    from a random start conserves each species there.  At 242^3 one buffer would exceed 4 GiB,
+    and set_geometry refuses the geometry."""
+    case = inputs.Case(name="all fluid 241^3", lattice="D3Q19", nx=241, ny=241, nz=241, tau_ref=3.0)
+    s = lbm_ms.Solver(case, precision="fp64")
+    info = s.get_info()
+    assert info.n_fluid == 241 ** 3
+    s.init(inputs.random_field(case.shape, seed=23, lo=0.2, hi=0.8))
+    inv, inflow, outflow = s.mass_balance()
+    s.step(1)
+    inv2, _, _ = s.mass_balance()
+    err = np.abs((inv2 - inv) - (inflow - outflow))
+    print("241^3 all fluid FP64: |change - (in - out)| = %s" % err)
+    assert np.all(err <= _conservation_tol("fp64", 19, info.n_fluid, inv))
+    assert np.all(np.isfinite(s.get_fields()))
+    s.close()
+    big = inputs.Case(name="all fluid 242^3", lattice="D3Q19", nx=242, ny=242, nz=242, tau_ref=3.0)
+    with pytest.raises(lbm_ms.LbmMsError) as e:
+        lbm_ms.Solver(big, precision="fp64")
+    assert "4 GiB" in str(e.value)
+
+
 def _conservation_tol(precision, q, n_fluid, inv):
     """Bound on |change of inventory - (inflow - outflow)| over one step from rounding alone.
     FP64: two tree reductions of the inventory, each within ~log2(N) eps of it.  FP32 storage: each
