@@ -229,7 +229,8 @@ size_t lbm_ms_batch_workspace_bytes(const lbm_ms_params* common, const lbm_ms_in
                                     int count);
 
 /* Create the batch: geometry clean-up, index maps, work lists and boundary data of every
- * instance.  E_GEOM names the first instance whose outlet is unreachable (lbm_ms_batch_last_error).
+ * instance.  On failure *out is NULL and lbm_ms_batch_last_error(NULL) tells why on this thread;
+ * E_GEOM names the first instance whose outlet is unreachable.
  * The caller owns d_workspace; the batch owns a stream of its own, ordered after common.stream
  * at every call and before it on return. */
 int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
@@ -277,6 +278,8 @@ int lbm_ms_batch_use_graphs(lbm_ms_batch_t b, int enable);
 const char* lbm_ms_batch_last_error(lbm_ms_batch_t b);
 void lbm_ms_batch_destroy(lbm_ms_batch_t b);
 
+/* The last error of handle h; with h == NULL, why the last lbm_ms_create, lbm_ms_batch_create or
+ * lbm_ms_workspace_bytes (returning 0) that failed on the calling thread failed. */
 const char* lbm_ms_last_error(lbm_ms_t h);
 const char* lbm_ms_status_string(int status);
 

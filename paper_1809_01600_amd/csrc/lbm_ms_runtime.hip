@@ -443,23 +443,42 @@ uint64_t param_hash(const lbm_ms_params& p, long long n_fluid)
 // ---------------------------------------------------------------------------------------------
 extern "C" {
 
+namespace {
+// Why the last create (or workspace query) on this thread failed: the calls that return no
+// handle report through it (lbm_ms_last_error / lbm_ms_batch_last_error with NULL).
+thread_local std::string g_create_err;
+int create_fail(int code, const std::string& why)
+{
+    g_create_err = why;
+    return code;
+}
+}  // namespace
+
 size_t lbm_ms_workspace_bytes(const lbm_ms_params* params)
 {
-    if (!valid_params(params, nullptr)) return 0;
+    std::string why;
+    if (!valid_params(params, &why)) {
+        g_create_err = "invalid parameters: " + why;
+        return 0;
+    }
     return layout(*params).total;
 }
 
 int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, lbm_ms_t* out)
 {
-    if (!out) return LBM_MS_E_ARG;
+    g_create_err.clear();
+    if (!out) return create_fail(LBM_MS_E_ARG, "out is NULL");
     *out = nullptr;
     std::string why;
-    if (!valid_params(params, &why)) return LBM_MS_E_ARG;
-    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return LBM_MS_E_ARG;
+    if (!valid_params(params, &why)) return create_fail(LBM_MS_E_ARG, "invalid parameters: " + why);
+    if (!d_workspace || ((uintptr_t)d_workspace & 255))
+        return create_fail(LBM_MS_E_ARG, "workspace is NULL or not 256-byte aligned");
     const Layout L = layout(*params);
-    if (bytes < L.total) return LBM_MS_E_NOMEM;
+    if (bytes < L.total)
+        return create_fail(LBM_MS_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes, " +
+                                               std::to_string(L.total) + " needed");
     lbm_ms_s* h = new (std::nothrow) lbm_ms_s();
-    if (!h) return LBM_MS_E_NOMEM;
+    if (!h) return create_fail(LBM_MS_E_NOMEM, "host allocation failed");
     h->p = *params;
     h->stream = (hipStream_t)params->stream;
     h->L = L;
@@ -468,7 +487,10 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
     h->N = (long long)params->nx * params->ny * params->nz;
     h->ty = default_tile_y(*params);
     h->cz = default_chunk_z(*params);
-    if (!tile_ok(params->lattice, h->ty, h->cz)) { delete h; return LBM_MS_E_ARG; }
+    if (!tile_ok(params->lattice, h->ty, h->cz)) {
+        delete h;
+        return create_fail(LBM_MS_E_ARG, "tile shape not among lbm_ms_tile_options for this lattice");
+    }
     h->tau_min = params->tau_min > 0 ? params->tau_min : 0.5 + 1e-9;
     h->tau_max = params->tau_max > 0 ? params->tau_max : 1e6;
     // lattice units: dt from tau_ref for the fastest pair (Eq. 25 with c_s^2 = 1/3)
@@ -476,12 +498,15 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
     h->dt = (params->tau_ref - 0.5) * params->dx * params->dx / (3.0 * Dmax);
     for (int i = 0; i < 9; ++i) h->Dl[i] = params->D[i] * h->dt / (params->dx * params->dx);
     h->Ct = params->p / (R_GAS * params->T);
-    if (hipHostMalloc((void**)&h->pinned, 4096) != hipSuccess) { delete h; return LBM_MS_E_HIP; }
+    if (hipHostMalloc((void**)&h->pinned, 4096) != hipSuccess) {
+        delete h;
+        return create_fail(LBM_MS_E_HIP, "hipHostMalloc of the pinned readback page failed");
+    }
     // clear the flag words
     if (hipMemsetAsync(h->at(L.flags), 0, 64, h->stream) != hipSuccess) {
         hipHostFree(h->pinned);
         delete h;
-        return LBM_MS_E_HIP;
+        return create_fail(LBM_MS_E_HIP, "hipMemsetAsync of the flag words failed");
     }
     *out = h;
     return LBM_MS_OK;
@@ -495,7 +520,11 @@ void lbm_ms_destroy(lbm_ms_t h)
     delete h;
 }
 
-const char* lbm_ms_last_error(lbm_ms_t h) { return h ? h->err.c_str() : "null handle"; }
+const char* lbm_ms_last_error(lbm_ms_t h)
+{
+    if (h) return h->err.c_str();
+    return g_create_err.empty() ? "null handle" : g_create_err.c_str();
+}
 
 const char* lbm_ms_status_string(int s)
 {
@@ -1216,8 +1245,11 @@ size_t lbm_ms_batch_workspace_bytes(const lbm_ms_params* common, const lbm_ms_in
                                     int count)
 {
     size_t total = 0;
-    if (!batch_layout(common, inst, count, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &total))
+    if (!batch_layout(common, inst, count, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &total)) {
+        g_create_err = "invalid batch parameters (D2Q9 common parameters, count > 0, every instance "
+                       "valid with a solid mask)";
         return 0;
+    }
     return total;
 }
 
@@ -1236,15 +1268,21 @@ void lbm_ms_batch_destroy(lbm_ms_batch_t b)
 int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
                         void* d_workspace, size_t bytes, lbm_ms_batch_t* out)
 {
-    if (!out) return LBM_MS_E_ARG;
+    g_create_err.clear();
+    if (!out) return create_fail(LBM_MS_E_ARG, "out is NULL");
     *out = nullptr;
     std::vector<size_t> offs;
     size_t ot, oti, oe, tc, ec, total;
-    if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &tc, &ec, &total)) return LBM_MS_E_ARG;
-    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return LBM_MS_E_ARG;
-    if (bytes < total) return LBM_MS_E_NOMEM;
+    if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &tc, &ec, &total))
+        return create_fail(LBM_MS_E_ARG, "invalid batch parameters (D2Q9 common parameters, "
+                                         "count > 0, every instance valid with a solid mask)");
+    if (!d_workspace || ((uintptr_t)d_workspace & 255))
+        return create_fail(LBM_MS_E_ARG, "workspace is NULL or not 256-byte aligned");
+    if (bytes < total)
+        return create_fail(LBM_MS_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes, " +
+                                               std::to_string(total) + " needed");
     lbm_ms_batch_s* b = new (std::nothrow) lbm_ms_batch_s();
-    if (!b) return LBM_MS_E_NOMEM;
+    if (!b) return create_fail(LBM_MS_E_NOMEM, "host allocation failed");
     b->common = *common;
     b->user = (hipStream_t)common->stream;
     b->ws = (char*)d_workspace;
@@ -1261,7 +1299,7 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
         lbm_ms_batch_destroy(b);
-        return LBM_MS_E_HIP;
+        return create_fail(LBM_MS_E_HIP, "stream or event creation failed");
     }
     rc = b->enter();
     for (int k = 0; k < count && rc == LBM_MS_OK; ++k) {
@@ -1284,16 +1322,19 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     }
     if (rc == LBM_MS_OK) rc = b->upload_tables();
     if (rc) {
-        const std::string e = b->err;
+        const std::string e = b->err.empty() ? std::string(lbm_ms_status_string(rc)) : b->err;
         lbm_ms_batch_destroy(b);
-        (void)e;
-        return rc;
+        return create_fail(rc, e);
     }
     *out = b;
     return b->leave(LBM_MS_OK);
 }
 
-const char* lbm_ms_batch_last_error(lbm_ms_batch_t b) { return b ? b->err.c_str() : "null batch"; }
+const char* lbm_ms_batch_last_error(lbm_ms_batch_t b)
+{
+    if (b) return b->err.c_str();
+    return g_create_err.empty() ? "null batch" : g_create_err.c_str();
+}
 
 lbm_ms_t lbm_ms_batch_instance(lbm_ms_batch_t b, int k)
 {

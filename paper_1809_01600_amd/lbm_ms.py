@@ -246,7 +246,7 @@ class Solver:
                                   tau_min, tau_max, tile_y, chunk_z, self.stream.cuda_stream)
         nbytes = lib().lbm_ms_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
-            raise LbmMsError(E_ARG, "invalid parameters")
+            raise LbmMsError(E_ARG, lib().lbm_ms_last_error(None).decode())
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.torch_device)
         h = _VP()
         self._check(lib().lbm_ms_create(ctypes.byref(self.params),
@@ -266,6 +266,8 @@ class Solver:
             msg = lib().lbm_ms_status_string(rc).decode()
             if handle and getattr(self, "h", None):
                 msg += ": " + lib().lbm_ms_last_error(self.h).decode()
+            elif not handle:  # a failed create: the library keeps its reason per thread
+                msg += ": " + lib().lbm_ms_last_error(None).decode()
             raise LbmMsError(rc, msg)
         return rc
 
@@ -438,14 +440,15 @@ class Batch:
             d.j_A_per_m2 = c.j_A_m2
         nbytes = lib().lbm_ms_batch_workspace_bytes(ctypes.byref(self.params), self.desc, n)
         if nbytes == 0:
-            raise LbmMsError(E_ARG, "invalid batch parameters")
+            raise LbmMsError(E_ARG, lib().lbm_ms_batch_last_error(None).decode())
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=torch.device(device))
         b = _VP()
         rc = lib().lbm_ms_batch_create(ctypes.byref(self.params), self.desc, n,
                                        ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                        ctypes.byref(b))
         if rc != OK:
-            raise LbmMsError(rc, lib().lbm_ms_status_string(rc).decode())
+            raise LbmMsError(rc, lib().lbm_ms_status_string(rc).decode() + ": " +
+                             lib().lbm_ms_batch_last_error(None).decode())
         self.b = b
         self.count = n
 

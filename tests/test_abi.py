@@ -108,3 +108,18 @@ def test_box_size_limit_of_the_index_offsets():
     assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(lbm_ms.make_params(ok, precision=lbm_ms.FP32))) > 0
     big = inputs.Case(name="too big", lattice="D3Q19", nx=1024, ny=1024, nz=1025)
     assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(lbm_ms.make_params(big, precision=lbm_ms.FP32))) == 0
+
+
+def test_failed_creates_report_why():
+    """Calls that return no handle keep their reason per thread (lbm_ms_last_error(NULL))."""
+    c = inputs.stefan_tube()
+    p = lbm_ms.make_params(c)
+    p.nu[2] = 1
+    assert lbm_ms.lib().lbm_ms_workspace_bytes(ctypes.byref(p)) == 0
+    assert b"equimolar" in lbm_ms.lib().lbm_ms_last_error(None)
+    h = ctypes.c_void_p()
+    assert lbm_ms.lib().lbm_ms_create(ctypes.byref(lbm_ms.make_params(c)), None, 0, ctypes.byref(h)) == lbm_ms.E_ARG
+    assert not h.value
+    assert b"256-byte aligned" in lbm_ms.lib().lbm_ms_last_error(None)
+    assert lbm_ms.lib().lbm_ms_batch_workspace_bytes(ctypes.byref(lbm_ms.make_params(c)), None, 0) == 0
+    assert b"invalid batch parameters" in lbm_ms.lib().lbm_ms_batch_last_error(None)

@@ -143,3 +143,17 @@ def test_autotune_keeps_results_bitwise(tmp_path, monkeypatch):
     tb = autotune.tune_batch(b, steps=5, warmup=1)
     assert tb[0] in (4, 8, 16)
     b.close()
+
+
+def test_create_names_the_instance_without_a_path():
+    """A failed batch create returns no handle; its reason, naming the instance whose outlet the
+    inlet cannot reach, comes from lbm_ms_batch_last_error(NULL)."""
+    import dataclasses
+    cases = _cases(seed0=500, sizes=((70, 33), (64, 40)), js=(1.0, 1.0))
+    wall = cases[1].mask().copy()
+    wall[:, :, 30] = 1  # a solid column across the slice
+    blocked = dataclasses.replace(cases[1], solid=wall)
+    with pytest.raises(lbm_ms.LbmMsError) as e:
+        lbm_ms.Batch([cases[0], blocked], precision="fp32")
+    assert e.value.status == lbm_ms.E_GEOM
+    assert "instance 1" in str(e.value)
