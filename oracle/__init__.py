@@ -22,6 +22,7 @@ Parity status of each function (what pins it is in the tests that name it):
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 import subprocess
 from typing import Optional
@@ -51,6 +52,7 @@ class _Params(ctypes.Structure):
         ("ms_mode", ctypes.c_int),
         ("eps", ctypes.c_double),
         ("tau_min", ctypes.c_double), ("tau_max", ctypes.c_double),
+        ("S", ctypes.c_double * 2), ("src_x0", ctypes.c_int),
     ]
 
 
@@ -175,6 +177,7 @@ class Oracle:
             n_open = int((mask[:, :, -1] == 0).sum())
         self.solid = np.ascontiguousarray(mask, dtype=np.uint8)
         self.n_open = n_open
+        self.n_source = 0
         self.lp = lattice_params(case, n_open)
         self.e, self.w = velocities(case.lattice)
         self.q = len(self.w)
@@ -193,11 +196,34 @@ class Oracle:
         p.ms_mode = ms_mode
         p.eps = default_eps(Q) if eps is None else eps
         p.tau_min, p.tau_max = tau_min, tau_max
+        p.S[0], p.S[1], p.src_x0 = 0.0, 0.0, case.nx  # no volumetric source
         self.p = p
         self.N = case.nx * case.ny * case.nz
         self.f = np.zeros((2, self.q) + case.shape)
         self.t = 0
         self.last = _Stats()
+
+    def set_source(self, x_first: int, j_A_cm2: float):
+        """Reaction spread uniformly over the fluid nodes of the columns x >= x_first (a functional
+        layer next to the electrolyte): the source term of Eq. 27, F_a = w_a S_s, on every such
+        node.  The layer's total per step equals the electrode flux of Eq. 39 at current density
+        j over the whole face (the superficial current): with N_s = -nu_s I / (n F),
+        S_s = -N_s dt n_face / (C_t dx n_layer).  x_first = nx removes the source."""
+        if not 0 <= x_first <= self.case.nx:
+            raise ValueError("x_first outside [0, nx]")
+        if x_first == self.case.nx:
+            self.p.S[0] = self.p.S[1] = 0.0
+            self.p.src_x0 = x_first
+            self.n_source = 0
+            return
+        n_layer = int((self.solid[:, :, x_first:] == 0).sum())
+        if n_layer == 0:
+            raise ValueError("no fluid node in the source layer")
+        lp = lattice_params(dataclasses.replace(self.case, j_A_cm2=j_A_cm2), self.n_open)
+        S = -lp["N"][:2] * lp["dt"] * lp["n_face"] / (lp["Ct"] * self.case.dx * n_layer)
+        self.p.S[0], self.p.S[1] = float(S[0]), float(S[1])
+        self.p.src_x0 = x_first
+        self.n_source = n_layer
 
     # -- initial states ---------------------------------------------------------------------
     def init_uniform(self):

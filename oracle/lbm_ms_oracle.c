@@ -23,7 +23,8 @@
  *   4. effective diffusivity of each evolved species from Eq. 24 with the flux vectors replaced
  *      by signed norms N_i -> -sgn(nu_i) |N_i|.
  *   5. relaxation time tau_i = D_i / c_s^2 + 1/2 with c_s^2 = 1/3 (Eq. 25).
- *   6. BGK collision toward f_eq = w_a X_s (Eq. 28 with Eq. 29).
+ *   6. BGK collision toward f_eq = w_a X_s (Eq. 28 with Eq. 29), plus the source term of Eq. 27,
+ *      F_a = w_a S_s, on the fluid nodes of the columns x >= src_x0 (zero unless a source is set).
  *   7. streaming; half-way bounce-back on solid links (Sec. 3.3, last paragraph).
  *   8. inlet: anti-bounce-back f_a = (w_a + w_abar) X_in - f_abar (Eq. 36);
  *      outlet: exact-flux rule f_a = f*_abar - (w_abar / W_n) Q_s imposing the electrode flux
@@ -45,6 +46,8 @@ typedef struct {
     int ms_mode;          /* 0: flux-norm ratio from the local fluxes, 1: stoichiometric ratio */
     double eps;           /* regularizer of the flux-norm ratio (lattice units) */
     double tau_min, tau_max;
+    double S[2];          /* source per fluid node and step of the columns x >= src_x0 (Eq. 27) */
+    int src_x0;
 } orc_params;
 
 typedef struct {
@@ -294,11 +297,12 @@ static int collide_all(const orc_params* p, const orc_lattice* L, const uint8_t*
                     for (int s = 0; s < 2; ++s)
                         for (int d = 0; d < 3; ++d) J_out[((long)s * 3 + d) * N + n] = J[s][d];
 
-                /* step 6: BGK collision toward w_a X_s */
+                /* step 6: BGK collision toward w_a X_s, and the source term w_a S_s (Eq. 27) */
                 for (int s = 0; s < 2; ++s)
                     for (int a = 0; a < q; ++a) {
                         long k = ((long)s * q + a) * N + n;
                         fstar[k] = f[k] - (f[k] - L->w[a] * Xn[s]) / tau[s];
+                        if (x >= p->src_x0) fstar[k] += L->w[a] * p->S[s];
                     }
             }
     free(X);
