@@ -104,6 +104,9 @@ typedef struct {
     int q;                /* velocities of the lattice */
     int tile_x, tile_y, chunk_z; /* launch shape in use */
     size_t workspace_bytes;
+    double S[2];          /* volumetric source per fluid node and step, species 1 and 2 ... */
+    int64_t n_source;     /* ... on these fluid nodes ... */
+    int source_x0;        /* ... of the columns x >= source_x0 (nx: no source) */
 } lbm_ms_info;
 
 /* Device bytes the caller must provide for these parameters (0 if the parameters are invalid). */
@@ -137,6 +140,20 @@ int lbm_ms_get_geometry(lbm_ms_t h, uint8_t* solid_host);
  * (Eq. 39).  Per open outlet node the lattice flux is Q_s = N_s dt / (C_t dx) * (ny nz / open
  * outlet nodes), so the outlet face carries the superficial current.  Call after set_geometry. */
 int lbm_ms_set_bc(lbm_ms_t h, const double X_in[3], double j_A_per_m2);
+
+/* Volumetric source (Eq. 27, F_a = w_a S_s): the reaction spread uniformly over the fluid nodes of
+ * the columns x >= x_first, a functional layer next to the electrolyte, instead of (or besides)
+ * the electrode flux at the outlet face.  The layer's total per step equals the electrode flux
+ * of Eq. 39 at current density j [A/m^2] over the whole face, so per fluid node of the layer
+ * S_s = -N_s dt n_face / (C_t dx n_layer) with N_s = -nu_s j / (n F): H2 is consumed, H2O made.
+ * For reaction in the layer alone, give the outlet j = 0 in lbm_ms_set_bc (a closed face).
+ * Set it before lbm_ms_init: the stored state is post-collision, so init places the first
+ * collision's source on the layer, and the read-back of fields, outlet means and inventory
+ * reports the mole fractions before each step's source, as the streamed state holds them.
+ * x_first = nx removes the source; lbm_ms_set_geometry clears it.  E_ARG for x_first outside
+ * [0, nx], j < 0, or a layer without fluid; E_STATE before lbm_ms_set_geometry.  Not for batch
+ * members (their argument tables are set at lbm_ms_batch_create). */
+int lbm_ms_set_source(lbm_ms_t h, int x_first, double j_A_per_m2);
 
 /* Initial state f_a = w_a X0 (equilibrium).  X0 == NULL: uniform inlet composition.  Otherwise
  * X0 holds [3][N] float64 mole fractions (species 3 is ignored), in host memory

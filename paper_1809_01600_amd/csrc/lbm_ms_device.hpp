@@ -173,6 +173,8 @@ struct StepArgs {
     double om_lo, om_hi;      // 1 / tau_max, 1 / tau_min (relaxation-time clamp)
     int ms_mode;              // 0 local flux norms, 1 stoichiometric ratio
     int inlet_wall;           // 1: x = 0 face is a bounce-back wall
+    double S0, S1;            // volumetric source per fluid node and step (Eq. 27) ...
+    int src_x0;               // ... on the columns x >= src_x0 (nx: none)
 };
 
 // Map the hardware block index to a tile so that each of the 8 XCDs (blocks are dealt to XCDs
@@ -533,14 +535,16 @@ __device__ inline double grad1(bool up, bool dn, double xu, double xc, double xd
     return 0.0;
 }
 
-// BGK collision toward w_a X_s (Eq. 28-29) and store of the post-collision populations.
-// NODE shift: f holds g_a = f_a - w_a X, so f*_a = w_a X + (1 - omega) g_a; the deviations are
-// rounded to the storage precision and the node reference c = X - sum_a h_a (FP64) keeps the
-// stored moment equal to X whatever the rounding.
+// BGK collision toward w_a X_s (Eq. 28-29) plus the source term w_a S_s of Eq. 27 (s0, s1; zero
+// off the reaction layer), and store of the post-collision populations.  The source enters as
+// a shift of the equilibrium: f + omega (w X - f) + w S = f + omega (w (X + S / omega) - f).
+// NODE shift: f holds g_a = f_a - w_a X, so f*_a = w_a (X + S) + (1 - omega) g_a; the deviations
+// are rounded to the storage precision and the node reference c = X + S - sum_a h_a (FP64)
+// keeps the stored moment equal to X + S whatever the rounding.
 template <class L, int P, bool NS>
 __device__ inline void collide_store(const StepArgs& a, int n,
                                      typename Codec<P>::CT (&f)[2][L::Q], double X0, double X1,
-                                     double om0, double om1)
+                                     double om0, double om1, double s0, double s1)
 {
     using C = Codec<P>;
     using CT = typename C::CT;
@@ -564,9 +568,13 @@ __device__ inline void collide_store(const StepArgs& a, int n,
             gstore<raw>(fout, off, r0);
             gstore<raw>(fout, off + spec, r1);
         }
-        gstore<double>(a.xout, (unsigned)n * 8u, X0 - (double)sh0);
-        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 - (double)sh1);
+        gstore<double>(a.xout, (unsigned)n * 8u, X0 + s0 - (double)sh0);
+        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 + s1 - (double)sh1);
         return;
+    }
+    if (s0 != 0.0 || s1 != 0.0) {  // only on the reaction layer
+        X0 += s0 * rcp64(om0);
+        X1 += s1 * rcp64(om1);
     }
     const CT o0 = (CT)om0, o1 = (CT)om1;
     const CT x0 = (CT)X0, x1 = (CT)X1;

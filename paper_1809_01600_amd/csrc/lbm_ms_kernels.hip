@@ -240,7 +240,8 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
         bool hit;
         ms_relax<2>(a, X0, X1, g0, g1, BND && x0 + cx - 1 == a.nx - 1, om0, om1, hit);
         if (hit) gstore<unsigned>(a.flags, 0u, 1u);
-        collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1);
+        const bool src = x0 + cx - 1 >= a.src_x0;
+        collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
     };
     if (edge)
         rest(std::true_type{});
@@ -445,7 +446,8 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
             bool hit;
             ms_relax<3>(a, Xc0, Xc1, g0, g1, x == a.nx - 1, om0, om1, hit);
             if (hit) gstore<unsigned>(a.flags, 0u, 1u);
-            collide_store<L, P, NS>(a, ic, fc, Xc0, Xc1, om0, om1);
+            const bool src = x >= a.src_x0;
+            collide_store<L, P, NS>(a, ic, fc, Xc0, Xc1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
         }
         Xm0 = Xc0; Xm1 = Xc1;
         Xc0 = Xp0; Xc1 = Xp1;
@@ -474,8 +476,11 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
          n += (long long)gridDim.x * blockDim.x) {
         const int i = a.idx[n];
         if (i < 0) continue;
-        const double v0 = X ? X[n] : u0;
-        const double v1 = X ? X[N + n] : u1;
+        // the stored state is post-collision: on the reaction layer the first collision of an
+        // equilibrium start adds the source (Eq. 27) and nothing else
+        const bool src = (int)(n % a.nx) >= a.src_x0;
+        const double v0 = (X ? X[n] : u0) + (src ? a.S0 : 0.0);
+        const double v1 = (X ? X[N + n] : u1) + (src ? a.S1 : 0.0);
         const float c0 = (float)a.c0, c1 = (float)a.c1;
         if constexpr (NS) {  // reference c = X, deviations zero
             a.xout[i] = v0;
@@ -663,8 +668,10 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
             } else {
                 double m0, m1;
                 node_moments<L, P, NS>(a, i, m0, m1);
-                v[0] += m0;
-                v[1] += m1;
+                // mole fractions before this step's source (the stored state is post-collision)
+                const bool src = x >= a.src_x0;
+                v[0] += m0 - (src ? a.S0 : 0.0);
+                v[1] += m1 - (src ? a.S1 : 0.0);
                 v[2] += 1.0;
                 v[5] += cross0;
                 v[6] += cross1;
@@ -685,6 +692,10 @@ __global__ void k_fields(StepArgs a, double* X)
         const int i = a.idx[n];
         if (i >= 0) {
             node_moments<L, P, NS>(a, i, X0, X1);
+            if ((int)(n % a.nx) >= a.src_x0) {  // before this step's source (post-collision state)
+                X0 -= a.S0;
+                X1 -= a.S1;
+            }
             X2 = 1.0 - X0 - X1;
         }
         X[n] = X0;

@@ -143,6 +143,9 @@ struct lbm_ms_s {
     long long n_fluid = 0, n_open = 0;
     double dt = 0, Ct = 0, Dl[9] = {0}, Q[2] = {0, 0}, Qs[2] = {0, 0}, Xin[3] = {0, 0, 0};
     double j = 0, eps = 0, tau_min = 0, tau_max = 0;
+    double S[2] = {0, 0};   // volumetric source per fluid node and step of the columns x >= src_x0
+    int src_x0 = 1 << 30;   // no source
+    long long n_src = 0;
     bool geom = false, bc = false, ready = false;
     long long steps = 0, snap_step = 0;
     int ty = 0, cz = 0;
@@ -206,6 +209,9 @@ struct lbm_ms_s {
         a.om_hi = 1.0 / tau_min;
         a.ms_mode = p.ms_mode;
         a.inlet_wall = p.inlet_mode == LBM_MS_INLET_WALL ? 1 : 0;
+        a.S0 = S[0];
+        a.S1 = S[1];
+        a.src_x0 = src_x0 < p.nx ? src_x0 : p.nx;
         return a;
     }
     int nblocks_step() const
@@ -597,6 +603,9 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
     std::vector<int32_t> idx;
     h->n_fluid = build_index(h->mask, idx);
     h->P = plane_pitch(h->n_fluid);
+    h->S[0] = h->S[1] = 0.0;  // a source layer belongs to the geometry it was set on
+    h->src_x0 = 1 << 30;
+    h->n_src = 0;
     // the kernels address a population buffer and the NODE-shift references with 32-bit byte
     // offsets from their bases
     const unsigned long long fbytes = 2ull * h->q * (unsigned long long)h->P * elem_bytes(h->p.precision);
@@ -669,6 +678,28 @@ int lbm_ms_set_bc(lbm_ms_t h, const double X_in[3], double j)
     h->eps = h->p.eps_flux >= 0 ? h->p.eps_flux
                                 : 1e-2 * std::max(std::fabs(h->Q[0]), std::fabs(h->Q[1])) + 1e-14;
     h->bc = true;
+    return h->upload_tables();
+}
+
+int lbm_ms_set_source(lbm_ms_t h, int x_first, double j)
+{
+    if (!h) return LBM_MS_E_ARG;
+    if (!h->geom) return h->fail(LBM_MS_E_STATE, "set_geometry first");
+    if (x_first < 0 || x_first > h->p.nx) return h->fail(LBM_MS_E_ARG, "x_first must lie in [0, nx]");
+    if (!(j >= 0.0) || !std::isfinite(j)) return h->fail(LBM_MS_E_ARG, "j must be finite and >= 0");
+    long long n = 0;
+    for (long long k = 0; k < h->N; ++k)
+        if (!h->mask[k] && (int)(k % h->p.nx) >= x_first) ++n;
+    if (x_first < h->p.nx && n == 0) return h->fail(LBM_MS_E_ARG, "no fluid node in the source layer");
+    h->n_src = x_first < h->p.nx ? n : 0;
+    h->src_x0 = x_first < h->p.nx ? x_first : (1 << 30);
+    // the layer's total per step is the electrode flux of Eq. 39 over the whole face:
+    // S_s = -N_s dt n_face / (C_t dx n_layer), N_s = -nu_s j / (n F)
+    const double face = (double)h->p.ny * h->p.nz;
+    for (int s = 0; s < 2; ++s) {
+        const double Ns = -(double)h->p.nu[s] * j / (h->p.n_electrons * FARADAY);
+        h->S[s] = h->n_src > 0 ? -Ns * h->dt * face / (h->Ct * h->p.dx * (double)h->n_src) : 0.0;
+    }
     return h->upload_tables();
 }
 
@@ -906,7 +937,8 @@ int lbm_ms_mass_balance(lbm_ms_t h, double inventory[2], double inflow[2], doubl
     if (rc) return rc;
     rc = faces(h, f);
     if (rc) return rc;
-    if (inventory) { inventory[0] = v[2]; inventory[1] = v[3]; }
+    // the stored state is post-collision: the layer's nodes hold this step's source already
+    if (inventory) { inventory[0] = v[2] - (double)h->n_src * h->S[0]; inventory[1] = v[3] - (double)h->n_src * h->S[1]; }
     if (inflow) { inflow[0] = f[3]; inflow[1] = f[4]; }
     if (outflow) { outflow[0] = f[5]; outflow[1] = f[6]; }
     return LBM_MS_OK;
@@ -1036,6 +1068,10 @@ int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info)
     info->tile_y = h->ty;
     info->chunk_z = h->cz;
     info->workspace_bytes = h->L.total;
+    info->S[0] = h->S[0];
+    info->S[1] = h->S[1];
+    info->n_source = h->n_src;
+    info->source_x0 = h->src_x0 < h->p.nx ? h->src_x0 : h->p.nx;
     return LBM_MS_OK;
 }
 

@@ -65,6 +65,9 @@ class lbm_ms_info(ctypes.Structure):
         ("q", ctypes.c_int),
         ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("chunk_z", ctypes.c_int),
         ("workspace_bytes", ctypes.c_size_t),
+        ("S", ctypes.c_double * 2),
+        ("n_source", ctypes.c_int64),
+        ("source_x0", ctypes.c_int),
     ]
 
 
@@ -99,6 +102,7 @@ _SIGNATURES = [
                                              ctypes.POINTER(ctypes.c_uint8),
                                              ctypes.POINTER(ctypes.c_int64)]),
     ("lbm_ms_set_bc", ctypes.c_int, [_VP, _DP, ctypes.c_double]),
+    ("lbm_ms_set_source", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double]),
     ("lbm_ms_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_ms_init_paper_profile", ctypes.c_int, [_VP]),
     ("lbm_ms_paper_profile", ctypes.c_int, [_VP, _DP]),
@@ -299,6 +303,11 @@ class Solver:
     def set_bc(self, X_in: Sequence[float], j_A_m2: float):
         x = np.ascontiguousarray(X_in, dtype=np.float64)
         self._check(lib().lbm_ms_set_bc(self.h, _dp(x), float(j_A_m2)))
+
+    def set_source(self, x_first: int, j_A_m2: float):
+        """Reaction layer x >= x_first carrying the electrode flux of current density j (see
+        lbm_ms_set_source); x_first = nx removes it."""
+        self._check(lib().lbm_ms_set_source(self.h, int(x_first), float(j_A_m2)))
 
     def init(self, X0=None):
         """X0: None (uniform inlet composition), numpy [3, ...] (host) or torch tensor (device)."""
