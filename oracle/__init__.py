@@ -40,6 +40,9 @@ LOCAL_FLUX = 0
 STOICH = 1
 
 
+LATTICE_CODES = {"D2Q9": 0, "D3Q19": 1, "D2Q5": 2}
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int),
@@ -109,7 +112,7 @@ def _u8(a: np.ndarray):
 
 def velocities(lattice: str):
     """(e [Q,3] int, w [Q]) of the oracle's velocity set."""
-    code = 0 if lattice == "D2Q9" else 1
+    code = LATTICE_CODES[lattice]
     q = lib().orc_num_velocities(code)
     e = np.zeros((q, 3), dtype=np.int32)
     w = np.zeros(q)
@@ -124,7 +127,7 @@ def label(lattice: str, solid: np.ndarray):
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     nz, ny, nx = solid.shape
     out = np.empty_like(solid)
-    n_out = lib().orc_label(0 if lattice == "D2Q9" else 1, nx, ny, nz, _u8(solid), _u8(out))
+    n_out = lib().orc_label(LATTICE_CODES[lattice], nx, ny, nz, _u8(solid), _u8(out))
     return out, int(n_out)
 
 
@@ -182,7 +185,7 @@ class Oracle:
         self.e, self.w = velocities(case.lattice)
         self.q = len(self.w)
         p = _Params()
-        p.lattice = 0 if case.lattice == "D2Q9" else 1
+        p.lattice = LATTICE_CODES[case.lattice]
         p.nx, p.ny, p.nz = case.nx, case.ny, case.nz
         for i in range(3):
             for j in range(3):

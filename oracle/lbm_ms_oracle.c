@@ -36,7 +36,7 @@
 #include <string.h>
 
 typedef struct {
-    int lattice;          /* 0: D2Q9, 1: D3Q19 */
+    int lattice;          /* 0: D2Q9, 1: D3Q19, 2: D2Q5 */
     int nx, ny, nz;       /* nz = 1 for D2Q9 */
     double Dl[3][3];      /* lattice binary diffusivities D*_ij = D_ij dt / dx^2 (symmetric) */
     double X_in[2];       /* inlet mole fractions of the evolved species */
@@ -71,7 +71,18 @@ typedef struct {
 static void build_lattice(int lattice, orc_lattice* L)
 {
     memset(L, 0, sizeof(*L));
-    if (lattice == 0) {
+    if (lattice == 2) {
+        /* D2Q5 (the paper names it beside D2Q9 in Sec. 3.1): rest and the four axis links, with
+         * weights 1/3 and 1/6, which give sum_a w_a e_a e_a = I / 3 like D2Q9 */
+        static const int ex[5] = {0, 1, 0, -1, 0}, ey[5] = {0, 0, 1, 0, -1};
+        L->q = 5;
+        for (int a = 0; a < 5; ++a) {
+            L->e[a][0] = ex[a];
+            L->e[a][1] = ey[a];
+            L->e[a][2] = 0;
+            L->w[a] = (a == 0) ? 1.0 / 3.0 : 1.0 / 6.0;
+        }
+    } else if (lattice == 0) {
         L->q = 9;
         for (int a = 0; a < 9; ++a) {
             double ex = 0.0, ey = 0.0;
@@ -201,7 +212,7 @@ static int collide_all(const orc_params* p, const orc_lattice* L, const uint8_t*
 {
     const long N = (long)p->nx * p->ny * p->nz;
     const int q = L->q;
-    const int dims = (p->lattice == 0) ? 2 : 3;
+    const int dims = (p->lattice == 1) ? 3 : 2;
     double* X = (double*)malloc(sizeof(double) * 3 * N);
     if (!X) return -8;
     orc_moments(p, solid, f, X);

@@ -63,10 +63,10 @@ def test_constants_are_the_papers():
     assert c.n_electrons == vals["n_electrons"]
 
 
-@pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19)])
+@pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19), ("D2Q5", 5)])
 def test_velocity_set_isotropy(lat, q):
     e, w = oracle.velocities(lat)
-    d = 2 if lat == "D2Q9" else 3
+    d = 3 if lat == "D3Q19" else 2
     assert len(w) == q
     assert abs(w.sum() - 1.0) < 1e-15
     assert np.allclose((w[:, None] * e).sum(0), 0.0, atol=1e-16)
@@ -87,6 +87,9 @@ def _label_reference(lattice, solid):
     fluid = solid == 0
     if lattice == "D2Q9":
         lab, n = ndimage.label(fluid[0], structure=np.ones((3, 3)))
+        lab = lab[None]
+    elif lattice == "D2Q5":  # axis links only: 4-connectivity
+        lab, n = ndimage.label(fluid[0], structure=ndimage.generate_binary_structure(2, 1))
         lab = lab[None]
     else:
         lab, n = ndimage.label(fluid, structure=ndimage.generate_binary_structure(3, 2))
@@ -128,10 +131,12 @@ def _label_reference(lattice, solid):
 
 
 @pytest.mark.parametrize("lat,shape,seed", [("D2Q9", (1, 40, 30), 1), ("D2Q9", (1, 25, 33), 2),
-                                            ("D3Q19", (9, 11, 13), 3)])
+                                            ("D3Q19", (9, 11, 13), 3), ("D2Q5", (1, 40, 30), 4),
+                                            ("D2Q5", (1, 25, 33), 5)])
 def test_label_matches_scipy(lat, shape, seed):
     rng = np.random.default_rng(seed)
-    solid = (rng.random(shape) < (0.55 if lat == "D2Q9" else 0.7)).astype(np.uint8)
+    frac = {"D2Q9": 0.55, "D2Q5": 0.35, "D3Q19": 0.7}[lat]
+    solid = (rng.random(shape) < frac).astype(np.uint8)
     got, n_open = oracle.label(lat, solid)
     ref = _label_reference(lat, solid)
     assert np.array_equal(got, ref)
@@ -157,12 +162,14 @@ def test_binary_linear_profile():
     assert np.max(np.abs(X[1, 0, 0] - (0.3 + k * q / Dl12))) < 1e-12
 
 
+@pytest.mark.parametrize("lat", ["D2Q9", "D2Q5"])
 @pytest.mark.parametrize("tau", [1.0, 3.0])
-def test_exact_variance_d2q9(tau):
+def test_exact_variance_d2q9(tau, lat):
     """Gaussian pulse far from every boundary, constant tau (binary, stoichiometric ratio):
-    the per-axis second moment follows the exact lattice relation at every step."""
+    the per-axis second moment follows the exact lattice relation at every step.  The y-summed
+    populations of both 2D sets evolve as the same D1Q3 (x-marginal weights 1/6, 2/3, 1/6)."""
     n = 160
-    case = inputs.stefan_tube(nx=n, ny=n, tau_ref=tau, X_in=(0.5, 0.5, 0.0), j_A_cm2=0.0)
+    case = inputs.stefan_tube(nx=n, ny=n, tau_ref=tau, X_in=(0.5, 0.5, 0.0), j_A_cm2=0.0, lattice=lat)
     o = oracle.Oracle(case, ms_mode=oracle.STOICH)
     yy, xx = np.meshgrid(np.arange(n) - n / 2, np.arange(n) - n / 2, indexing="ij")
     s0 = 2.0
@@ -171,7 +178,10 @@ def test_exact_variance_d2q9(tau):
     X0[0, 0] += bump
     X0[1, 0] -= bump
     o.init_field(X0)
-    dX = o.moments()[0, 0] - 0.5
+    # deviations from the far field's own value (a node 80 cells from the pulse): the uniform
+    # state rounds to 0.5 only up to an ulp of the weights, an offset that the sum over x^2
+    # would magnify to 1e-9
+    dX = o.moments()[0, 0] - o.moments()[0, 0, 0, n // 2]
     M0 = dX.sum()
     var0x = (dX * xx ** 2).sum() / M0
     var0y = (dX * yy ** 2).sum() / M0
@@ -179,7 +189,7 @@ def test_exact_variance_d2q9(tau):
     for target in (1, 7, 40):
         o.step(target - t)
         t = target
-        dX = o.moments()[0, 0] - 0.5
+        dX = o.moments()[0, 0] - o.moments()[0, 0, 0, n // 2]
         assert abs(dX.sum() - M0) < 1e-13 * abs(M0) * 10
         vx = (dX * xx ** 2).sum() / dX.sum()
         vy = (dX * yy ** 2).sum() / dX.sum()
@@ -210,11 +220,13 @@ def test_exact_variance_d3q19():
         assert abs(got - cf.exact_variance(v, tau, 12)) < 1e-10 * got
 
 
-def test_stefan_chain_stoichiometric():
+@pytest.mark.parametrize("lat", ["D2Q9", "D2Q5"])
+def test_stefan_chain_stoichiometric(lat):
     """Strongly coupled ternary tube (long tube, X_1 falls from 0.6 to ~0.3): the time-stepped
-    steady state equals the exact discrete chain solved by Newton's method."""
+    steady state equals the exact discrete chain solved by Newton's method.  D2Q5 has the same
+    D1Q3 x-marginal as D2Q9, so its y-uniform steady state is the same chain."""
     nx = 40
-    case = inputs.stefan_tube(nx=nx, ny=1, dx=0.1 / nx, tau_ref=5.0, j_A_cm2=0.5)
+    case = inputs.stefan_tube(nx=nx, ny=1, dx=0.1 / nx, tau_ref=5.0, j_A_cm2=0.5, lattice=lat)
     o = oracle.Oracle(case, ms_mode=oracle.STOICH)
     o.init_uniform()
     X, _ = run_to_steady(o, window=4000)
@@ -267,7 +279,7 @@ def test_stefan_continuum_second_order(mode):
 # conservation
 # ----------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9))])
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17))])
 def test_closed_box_conserves(lat, shape):
     nz, ny, nx = shape
     case = inputs.random_small(nx, ny, nz, lat, seed=11, solid_frac=0.2, j_A_cm2=0.0)
@@ -280,7 +292,8 @@ def test_closed_box_conserves(lat, shape):
 
 
 @pytest.mark.parametrize("lat,shape,mode", [("D2Q9", (1, 16, 20), oracle.LOCAL_FLUX),
-                                            ("D3Q19", (5, 6, 10), oracle.STOICH)])
+                                            ("D3Q19", (5, 6, 10), oracle.STOICH),
+                                            ("D2Q5", (1, 16, 20), oracle.LOCAL_FLUX)])
 def test_open_mass_balance(lat, shape, mode):
     """Every step: inventory change = inflow - outflow, and the outflow is Q_s per open node."""
     nz, ny, nx = shape
