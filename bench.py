@@ -31,7 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # once and written once (pull scheme)
 BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16"): 72,
                   ("D2Q9", "bf16"): 72, ("D3Q19", "fp64"): 608, ("D3Q19", "fp32"): 304,
-                  ("D3Q19", "fp16"): 152, ("D3Q19", "bf16"): 152}
+                  ("D3Q19", "fp16"): 152, ("D3Q19", "bf16"): 152, ("D2Q5", "fp64"): 160,
+                  ("D2Q5", "fp32"): 80, ("D2Q5", "fp16"): 40, ("D2Q5", "bf16"): 40}
 NODE_SHIFT_BYTES = 2 * 8 * 2
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
                   "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
@@ -97,6 +98,8 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--shift", default="global", choices=["global", "node"])
     ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
+    ap.add_argument("--lattice", default="d2q9", choices=["d2q9", "d2q5"],
+                    help="velocity set of the porous_2d slice")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--chunk-z", type=int, default=0)
@@ -119,8 +122,9 @@ def main(argv=None):
         return run_batch(args)
     if args.workload == "porous_2d":
         case = inputs.porous_2d()
-        desc = ("porous anode slice D2Q9 1024x1024, overlapping disks r~U[4,12], void fraction "
-                "0.40, seed 2, X_in~Dirichlet(6,3,1), j=1.0 A/cm^2")
+        case.lattice = args.lattice.upper()
+        desc = ("porous anode slice %s 1024x1024, overlapping disks r~U[4,12], void fraction "
+                "0.40, seed 2, X_in~Dirichlet(6,3,1), j=1.0 A/cm^2" % case.lattice)
     else:
         case = inputs.porous_3d()
         desc = ("porous anode block D3Q19 256^3, overlapping spheres r~U[3,8], void fraction "
@@ -155,7 +159,7 @@ def main(argv=None):
     if shift == lbm_ms.SHIFT_NODE:  # FP64 node reference per evolved species, read and written
         bytes_per_launch += NODE_SHIFT_BYTES * n_fluid
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    wl_key = "%s_%s_%s" % (args.workload, args.precision, args.shift)
+    wl_key = "%s%s_%s_%s" % (args.workload, "_d2q5" if case.lattice == "D2Q5" else "", args.precision, args.shift)
     traffic = measured_traffic(wl_key, kernel_hash())
 
     ms_per_step = elapsed * 1e3 / K
@@ -195,7 +199,7 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step2d" if case.lattice == "D2Q9" else "k_step3d",
+            "kernel": "k_step3d" if case.lattice == "D3Q19" else "k_step2d",
             "kernel_us": round(kernel_ms * 1e3, 3),
             "bytes_per_launch": bytes_per_launch,
         },

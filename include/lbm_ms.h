@@ -50,7 +50,7 @@ typedef enum {
     LBM_MS_E_TAU_CLAMP = -9     /* a relaxation time hit tau_min / tau_max since the last check */
 } lbm_ms_status;
 
-enum { LBM_MS_D2Q9 = 0, LBM_MS_D3Q19 = 1 };
+enum { LBM_MS_D2Q9 = 0, LBM_MS_D3Q19 = 1, LBM_MS_D2Q5 = 2 };
 
 /* population storage (collision arithmetic is FP64 for LBM_MS_FP64, FP32 otherwise; the
  * Maxwell-Stefan solve, residual, mass balance and overpotential are FP64 in every mode) */
@@ -68,7 +68,7 @@ enum { LBM_MS_LOCAL_FLUX = 0, LBM_MS_STOICH = 1 };
 enum { LBM_MS_INLET_DIRICHLET = 0, LBM_MS_INLET_WALL = 1 };
 
 typedef struct {
-    int lattice;          /* LBM_MS_D2Q9 or LBM_MS_D3Q19 */
+    int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; not for batches) or LBM_MS_D3Q19 */
     int nx, ny, nz;       /* nodes; nz must be 1 for D2Q9; nx >= 2 */
     double T;             /* K */
     double p;             /* Pa; C_t = p / (R T), R = 8.3145 */

@@ -44,6 +44,23 @@ struct D2Q9 {
     static constexpr float wf[9] = {W0F, W1F, W1F, W1F, W1F, W2F, W2F, W2F, W2F};
 };
 
+// D2Q5, named beside D2Q9 in Sec. 3.1: rest and the four axis links in Eq. 2's order, weights
+// 1/3 and 1/6, the same second moment c_s^2 = 1/3 with five populations instead of nine.
+struct D2Q5 {
+    static constexpr int Q = 5;
+    static constexpr int DIMS = 2;
+    static constexpr int ex[5] = {0, 1, 0, -1, 0};
+    static constexpr int ey[5] = {0, 0, 1, 0, -1};
+    static constexpr int ez[5] = {0, 0, 0, 0, 0};
+    static constexpr int opp[5] = {0, 3, 4, 1, 2};
+    static constexpr double w[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    // FP32 weights with an exact unit sum: 1/6 rounded to float, the rest weight 1 - 4 w1 (a
+    // multiple of 2^-24 in [1/4, 1/2), so itself a float)
+    static constexpr float W1F = (float)(1.0 / 6);
+    static constexpr float W0F = (float)(1.0 - 4.0 * (double)W1F);
+    static constexpr float wf[5] = {W0F, W1F, W1F, W1F, W1F};
+};
+
 // D3Q19 with opposite links adjacent: rest, +-x, +-y, +-z, then the twelve edge vectors.
 struct D3Q19 {
     static constexpr int Q = 19;
@@ -81,7 +98,9 @@ constexpr double wf_sum()
     for (int k = 0; k < L::Q; ++k) t += (double)L::wf[k];
     return t;
 }
-static_assert(wf_sum<D2Q9>() == 1.0 && wf_sum<D3Q19>() == 1.0, "float weights must sum to one");
+static_assert(wf_sum<D2Q9>() == 1.0 && wf_sum<D3Q19>() == 1.0 && wf_sum<D2Q5>() == 1.0,
+              "float weights must sum to one");
+static_assert((double)D2Q5::W0F == 1.0 - 4.0 * (double)D2Q5::W1F, "D2Q5 rest weight is not a float");
 static_assert((double)D2Q9::W0F * (1LL << 25) == (double)((1LL << 25) - D2Q9::M1 - D2Q9::M2),
               "D2Q9 rest weight is not a float");
 static_assert((double)D3Q19::W0F * (1LL << 28) == (double)((1LL << 28) - 6 * D3Q19::M1 - 6 * D3Q19::M2),

@@ -115,15 +115,15 @@ __device__ inline void stage_plane_refs(const StepArgs& a, int x0, int y0, int* 
 
 // Pull of one node of a 2D tile: NODE-shift references from the staged region, else the plain
 // gather.  (cx, cy): the node's position in the staged region.
-template <int P, bool NS, int RX, int RY>
-__device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[D2Q9::Q], bool inlet,
-                                bool outlet, typename Codec<P>::CT (&f)[2][D2Q9::Q], double& X0,
+template <class L, int P, bool NS, int RX, int RY>
+__device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                                bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
                                 double& X1, const double* sc, int cx, int cy)
 {
     if constexpr (NS)
-        gather_ns<D2Q9, P>(a, i, si, inlet, outlet, f, X0, X1, RefLds<RX, RY>{sc, cy * RX + cx});
+        gather_ns<L, P>(a, i, si, inlet, outlet, f, X0, X1, RefLds<RX, RY>{sc, cy * RX + cx});
     else
-        gather<D2Q9, P, false>(a, i, si, inlet, outlet, f, X0, X1);
+        gather<L, P, false>(a, i, si, inlet, outlet, f, X0, X1);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -142,12 +142,11 @@ __device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[D2Q9::
 template <int P, bool NS>
 constexpr int step2d_min_blocks(int ty) { return (P != P_F64 && !NS) ? 64 / ty : 1; }
 
-template <int P, bool NS, int TY>
+template <class L, int P, bool NS, int TY>
 __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_step2d(const StepArgs* __restrict__ insts,
                                                     const int4* __restrict__ tiles,
                                                     const unsigned* __restrict__ ent)
 {
-    using L = D2Q9;
     using CT = typename Codec<P>::CT;
     constexpr int TX = 64, RX = TX + 4, RY = TY + 4, BS = 32 * TY;
     __shared__ int sI[RY * RX];
@@ -188,7 +187,7 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
             const int x = x0 + cxo - 1;
             int si[L::Q];
             nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
-            gather2d<P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && BND && x == 0, io >= 0 && BND && x == a.nx - 1,
+            gather2d<L, P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && BND && x == 0, io >= 0 && BND && x == a.nx - 1,
                                     f, X0, X1, sC, cxo + 1, cyo + 1);
         }
         if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
@@ -200,7 +199,7 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
             lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
             CT hf[2][L::Q];
             double h0, h1;
-            gather2d<P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && BND && x == 0, hi >= 0 && BND && x == a.nx - 1,
+            gather2d<L, P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && BND && x == 0, hi >= 0 && BND && x == a.nx - 1,
                                     hf, h0, h1, sC, cx + 1, cy + 1);
             if (job) {
                 sX[0][cy][cx] = h0;
@@ -217,7 +216,7 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_ste
             lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
             CT hf[2][L::Q];
             double h0, h1;
-            gather2d<P, NS, RX, RY>(a, hi, si, BND && x == 0, BND && x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
+            gather2d<L, P, NS, RX, RY>(a, hi, si, BND && x == 0, BND && x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
             sX[0][cy][cx] = h0;
             sX[1][cy][cx] = h1;
         }
@@ -826,32 +825,41 @@ static hipError_t launch_step_p(hipStream_t st, const StepArgs& a, int lattice, 
     return hipGetLastError();
 }
 
-template <int P, bool NS>
+template <class L, int P, bool NS>
 static hipError_t launch_step2d_p(hipStream_t st, const StepArgs* insts, const int4* tiles,
                                   const unsigned* ent, int ntiles, int ty)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (ty) {
-    case 4: hipLaunchKernelGGL((k_step2d<P, NS, 4>), dim3(ntiles), dim3(32 * 4), 0, st, insts, tiles, ent); break;
-    case 8: hipLaunchKernelGGL((k_step2d<P, NS, 8>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent); break;
-    case 16: hipLaunchKernelGGL((k_step2d<P, NS, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent); break;
+    case 4: hipLaunchKernelGGL((k_step2d<L, P, NS, 4>), dim3(ntiles), dim3(32 * 4), 0, st, insts, tiles, ent); break;
+    case 8: hipLaunchKernelGGL((k_step2d<L, P, NS, 8>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent); break;
+    case 16: hipLaunchKernelGGL((k_step2d<L, P, NS, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,
-                         const unsigned* ent, int ntiles, int prec, int node_shift, int ty)
+template <class L>
+static hipError_t launch_step2d_l(hipStream_t st, const StepArgs* insts, const int4* tiles,
+                                  const unsigned* ent, int ntiles, int prec, int node_shift, int ty)
 {
     switch (prec) {
-    case P_F64: return launch_step2d_p<P_F64, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_F32: return node_shift ? launch_step2d_p<P_F32, true>(st, insts, tiles, ent, ntiles, ty)
-                                  : launch_step2d_p<P_F32, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_F16: return node_shift ? launch_step2d_p<P_F16, true>(st, insts, tiles, ent, ntiles, ty)
-                                  : launch_step2d_p<P_F16, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_BF16: return node_shift ? launch_step2d_p<P_BF16, true>(st, insts, tiles, ent, ntiles, ty)
-                                   : launch_step2d_p<P_BF16, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F64: return launch_step2d_p<L, P_F64, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F32: return node_shift ? launch_step2d_p<L, P_F32, true>(st, insts, tiles, ent, ntiles, ty)
+                                  : launch_step2d_p<L, P_F32, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F16: return node_shift ? launch_step2d_p<L, P_F16, true>(st, insts, tiles, ent, ntiles, ty)
+                                  : launch_step2d_p<L, P_F16, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_BF16: return node_shift ? launch_step2d_p<L, P_BF16, true>(st, insts, tiles, ent, ntiles, ty)
+                                   : launch_step2d_p<L, P_BF16, false>(st, insts, tiles, ent, ntiles, ty);
     }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,
+                         const unsigned* ent, int ntiles, int lattice, int prec, int node_shift, int ty)
+{
+    if (lattice == 2) return launch_step2d_l<D2Q5>(st, insts, tiles, ent, ntiles, prec, node_shift, ty);
+    if (lattice == 0) return launch_step2d_l<D2Q9>(st, insts, tiles, ent, ntiles, prec, node_shift, ty);
     return hipErrorInvalidValue;
 }
 
@@ -859,10 +867,11 @@ int tile_options(int lattice, int* ty, int* cz, int cap)
 {
     static const int t2[3] = {4, 8, 16};
     static const int t3[4][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}};
-    const int total = (lattice == 0) ? 3 : 4;
+    const bool d2 = lattice != 1;  // D2Q9 and D2Q5 share the 2D launch shapes
+    const int total = d2 ? 3 : 4;
     for (int i = 0; i < total && i < cap; ++i) {
-        if (ty) ty[i] = (lattice == 0) ? t2[i] : t3[i][0];
-        if (cz) cz[i] = (lattice == 0) ? 0 : t3[i][1];
+        if (ty) ty[i] = d2 ? t2[i] : t3[i][0];
+        if (cz) cz[i] = d2 ? 0 : t3[i][1];
     }
     return total;
 }
@@ -893,6 +902,7 @@ static hipError_t dispatch(int lattice, int prec, int ns, Args&&... args)
     case P_BF16: return ns ? Fn<LAT, P_BF16, true>::run(args...) : Fn<LAT, P_BF16, false>::run(args...); \
     }
     if (lattice == 0) { LBMMS_CASES(D2Q9) }
+    else if (lattice == 2) { LBMMS_CASES(D2Q5) }
     else { LBMMS_CASES(D3Q19) }
 #undef LBMMS_CASES
     return hipErrorInvalidValue;

@@ -30,7 +30,12 @@ struct Layout {
     size_t tile_cap, ent_cap;
 };
 
-int q_of(int lattice) { return lattice == LBM_MS_D2Q9 ? 9 : 19; }
+int q_of(int lattice) { return lattice == LBM_MS_D2Q9 ? 9 : (lattice == LBM_MS_D2Q5 ? 5 : 19); }
+bool known_lattice(int lattice)
+{
+    return lattice == LBM_MS_D2Q9 || lattice == LBM_MS_D3Q19 || lattice == LBM_MS_D2Q5;
+}
+bool is_2d(int lattice) { return lattice != LBM_MS_D3Q19; }
 
 size_t elem_bytes(int prec)
 {
@@ -60,9 +65,9 @@ bool valid_params(const lbm_ms_params* p, std::string* why)
 {
     auto fail = [&](const char* m) { if (why) *why = m; return false; };
     if (!p) return fail("params is NULL");
-    if (p->lattice != LBM_MS_D2Q9 && p->lattice != LBM_MS_D3Q19) return fail("unknown lattice");
+    if (!known_lattice(p->lattice)) return fail("unknown lattice");
     if (p->nx < 2 || p->ny < 1 || p->nz < 1) return fail("need nx >= 2, ny >= 1, nz >= 1");
-    if (p->lattice == LBM_MS_D2Q9 && p->nz != 1) return fail("D2Q9 needs nz == 1");
+    if (is_2d(p->lattice) && p->nz != 1) return fail("the 2D lattices need nz == 1");
     const long long N = (long long)p->nx * p->ny * p->nz;
     // the kernels address the index map with 32-bit byte offsets from its base
     if (N > (1ll << 30)) return fail("domain too large (more than 2^30 voxels)");
@@ -115,7 +120,7 @@ Layout layout(const lbm_ms_params& p)
     // 2D work lists: tiles of 64 x TY (TY >= 4) and their entries
     L.tile_cap = 0;
     L.ent_cap = 0;
-    if (p.lattice == LBM_MS_D2Q9) tile_caps(p.nx, p.ny, &L.tile_cap, &L.ent_cap);
+    if (is_2d(p.lattice)) tile_caps(p.nx, p.ny, &L.tile_cap, &L.ent_cap);
     L.inst = take(2 * sizeof(StepArgs));
     L.tiles = take(L.tile_cap * 2 * sizeof(int4));
     L.ent = take(L.ent_cap * sizeof(uint32_t));
@@ -237,7 +242,7 @@ struct lbm_ms_s {
 
     int upload_tiles()
     {
-        if (p.lattice != LBM_MS_D2Q9 || !geom) return LBM_MS_OK;
+        if (!is_2d(p.lattice) || !geom) return LBM_MS_OK;
         std::vector<int4> tl;
         std::vector<uint32_t> en;
         build_tiles_2d(p.nx, p.ny, ty, mask, 0, 0, tl, en);
@@ -273,6 +278,10 @@ HostLattice host_lattice(int lattice)
         if (lattice == LBM_MS_D2Q9) {
             H.e[k][0] = D2Q9::ex[k];
             H.e[k][1] = D2Q9::ey[k];
+            H.e[k][2] = 0;
+        } else if (lattice == LBM_MS_D2Q5) {
+            H.e[k][0] = D2Q5::ex[k];
+            H.e[k][1] = D2Q5::ey[k];
             H.e[k][2] = 0;
         } else {
             H.e[k][0] = D3Q19::ex[k];
@@ -406,7 +415,7 @@ bool tiles_in_bounds(const std::vector<int4>& tiles, const std::vector<uint32_t>
 int default_tile_y(const lbm_ms_params& p)
 {
     if (p.tile_y > 0) return p.tile_y;
-    if (p.lattice == LBM_MS_D2Q9) return p.ny >= 8 ? 8 : 4;
+    if (is_2d(p.lattice)) return p.ny >= 8 ? 8 : 4;
     // measured on a 256^3 porous block: FP64 runs best with the 256-lane tiles (its 512-lane
     // build spills), every other storage mode with the 512-lane ones
     return p.precision == LBM_MS_FP64 ? 4 : 8;
@@ -414,7 +423,7 @@ int default_tile_y(const lbm_ms_params& p)
 
 int default_chunk_z(const lbm_ms_params& p)
 {
-    if (p.lattice == LBM_MS_D2Q9) return 0;
+    if (is_2d(p.lattice)) return 0;
     if (p.chunk_z > 0) return p.chunk_z;
     return p.nz >= 128 ? 32 : 16;
 }
@@ -551,31 +560,37 @@ const char* lbm_ms_status_string(int s)
 
 int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w)
 {
-    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
+    if (!known_lattice(lattice)) return LBM_MS_E_ARG;
     const int Q = q_of(lattice);
     if (q) *q = Q;
-    for (int k = 0; k < Q; ++k) {
-        if (e) {
-            e[3 * k + 0] = lattice == 0 ? D2Q9::ex[k] : D3Q19::ex[k];
-            e[3 * k + 1] = lattice == 0 ? D2Q9::ey[k] : D3Q19::ey[k];
-            e[3 * k + 2] = lattice == 0 ? D2Q9::ez[k] : D3Q19::ez[k];
+    auto put = [&](auto L) {
+        using Lat = decltype(L);
+        for (int k = 0; k < Q; ++k) {
+            if (e) {
+                e[3 * k + 0] = Lat::ex[k];
+                e[3 * k + 1] = Lat::ey[k];
+                e[3 * k + 2] = Lat::ez[k];
+            }
+            if (w) w[k] = Lat::w[k];
         }
-        if (w) w[k] = lattice == 0 ? D2Q9::w[k] : D3Q19::w[k];
-    }
+    };
+    if (lattice == LBM_MS_D2Q9) put(D2Q9{});
+    else if (lattice == LBM_MS_D2Q5) put(D2Q5{});
+    else put(D3Q19{});
     return LBM_MS_OK;
 }
 
 int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap)
 {
     (void)precision;
-    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
+    if (!known_lattice(lattice)) return LBM_MS_E_ARG;
     return tile_options(lattice, tile_y, chunk_z, cap);
 }
 
 int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z)
 {
     if (!h) return LBM_MS_E_ARG;
-    if (h->p.lattice == LBM_MS_D2Q9) chunk_z = 0;
+    if (is_2d(h->p.lattice)) chunk_z = 0;
     if (!tile_ok(h->p.lattice, tile_y, chunk_z))
         return h->fail(LBM_MS_E_ARG, "launch shape (%d, %d) not compiled", tile_y, chunk_z);
     h->ty = tile_y;
@@ -632,8 +647,8 @@ int lbm_ms_clean_geometry(int lattice, int nx, int ny, int nz, const uint8_t* so
                           uint8_t* solid_out, int64_t* n_open)
 {
     if (!solid_in || !solid_out || nx < 2 || ny < 1 || nz < 1) return LBM_MS_E_ARG;
-    if (lattice != LBM_MS_D2Q9 && lattice != LBM_MS_D3Q19) return LBM_MS_E_ARG;
-    if (lattice == LBM_MS_D2Q9 && nz != 1) return LBM_MS_E_ARG;
+    if (!known_lattice(lattice)) return LBM_MS_E_ARG;
+    if (is_2d(lattice) && nz != 1) return LBM_MS_E_ARG;
     lbm_ms_params p{};
     p.lattice = lattice;
     p.nx = nx;
@@ -781,8 +796,9 @@ int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
     const unsigned* ent = reinterpret_cast<const unsigned*>(h->ws + h->L.ent);
     for (int64_t t = 0; t < nsteps; ++t) {
         hipError_t e;
-        if (h->p.lattice == LBM_MS_D2Q9) {
-            e = launch_step2d(h->stream, tab + h->cur, tiles, ent, h->ntiles, h->prec(), h->ns(), h->ty);
+        if (is_2d(h->p.lattice)) {
+            e = launch_step2d(h->stream, tab + h->cur, tiles, ent, h->ntiles, h->p.lattice, h->prec(),
+                              h->ns(), h->ty);
         } else {
             StepArgs a = h->args(h->cur);
             e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb);
@@ -1177,7 +1193,7 @@ struct lbm_ms_batch_s {
     {
         const StepArgs* tab = reinterpret_cast<const StepArgs*>(ws + off_tab) + (size_t)cur * count;
         return launch_step2d(stream, tab, reinterpret_cast<const int4*>(ws + off_tiles),
-                             reinterpret_cast<const unsigned*>(ws + off_ent), ntiles,
+                             reinterpret_cast<const unsigned*>(ws + off_ent), ntiles, LBM_MS_D2Q9,
                              common.precision, node_shift(common) ? 1 : 0, ty);
     }
     void advance(int64_t n)

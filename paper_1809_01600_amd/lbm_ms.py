@@ -16,7 +16,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_ms.so")
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D2Q5 = 0, 1, 2
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D2Q5": D2Q5}
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5}
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 SHIFT_GLOBAL, SHIFT_NODE = 0, 1
 LOCAL_FLUX, STOICH = 0, 1
@@ -191,7 +193,7 @@ def clean_geometry(lattice: str, solid: np.ndarray):
     out = np.empty_like(solid)
     n_open = ctypes.c_int64(0)
     u8 = ctypes.POINTER(ctypes.c_uint8)
-    rc = lib().lbm_ms_clean_geometry(D2Q9 if lattice == "D2Q9" else D3Q19, nx, ny, nz,
+    rc = lib().lbm_ms_clean_geometry(LATTICES[lattice], nx, ny, nz,
                                      solid.ctypes.data_as(u8), out.ctypes.data_as(u8),
                                      ctypes.byref(n_open))
     if rc != OK:
@@ -212,7 +214,7 @@ def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
                 tile_y: int = 0, chunk_z: int = 0, stream: Optional[int] = None) -> lbm_ms_params:
     """Marshal a physical problem description (inputs.Case) into lbm_ms_params."""
     p = lbm_ms_params()
-    p.lattice = D2Q9 if case.lattice == "D2Q9" else D3Q19
+    p.lattice = LATTICES[case.lattice]
     p.nx, p.ny, p.nz = case.nx, case.ny, case.nz
     p.T, p.p = case.T, case.p
     D = case.D_matrix().reshape(-1)
@@ -258,7 +260,7 @@ class Solver:
                                         ctypes.byref(h)), handle=False)
         self.h = h
         self.N = case.nx * case.ny * case.nz
-        self.q = 9 if case.lattice == "D2Q9" else 19
+        self.q = Q_OF[case.lattice]
         if set_geometry:
             self.set_geometry(case.mask())
             if set_bc:

@@ -39,7 +39,7 @@ def test_cnn_symbols_exported_and_bound():
 
 
 def test_lattice_tables_match_the_oracle_as_sets():
-    for lat, name in ((lbm_ms.D2Q9, "D2Q9"), (lbm_ms.D3Q19, "D3Q19")):
+    for lat, name in ((lbm_ms.D2Q9, "D2Q9"), (lbm_ms.D3Q19, "D3Q19"), (lbm_ms.D2Q5, "D2Q5")):
         e, w = lbm_ms.lattice_info(lat)
         eo, wo = oracle.velocities(name)
         a = sorted((tuple(v), round(x, 15)) for v, x in zip(e.tolist(), w))
@@ -91,7 +91,9 @@ def test_missing_library_fails_loudly(monkeypatch):
 
 @pytest.mark.parametrize("lat,shape,frac,seed", [("D2Q9", (1, 40, 30), 0.55, 1),
                                                  ("D2Q9", (1, 64, 64), 0.45, 2),
-                                                 ("D3Q19", (9, 11, 13), 0.7, 3)])
+                                                 ("D3Q19", (9, 11, 13), 0.7, 3),
+                                                 ("D2Q5", (1, 40, 30), 0.35, 4),
+                                                 ("D2Q5", (1, 64, 64), 0.3, 5)])
 def test_host_clean_up_matches_oracle_labelling(lat, shape, frac, seed):
     rng = np.random.default_rng(seed)
     solid = (rng.random(shape) < frac).astype(np.uint8)

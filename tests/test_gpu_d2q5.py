@@ -1,0 +1,126 @@
+"""The D2Q5 lattice (rest and axis links, weights 1/3 and 1/6; named beside D2Q9 in Sec. 3.1) on
+the GPU through the C ABI, against the oracle's D2Q5 (pinned on the CPU: isotropy, exact
+variance, the discrete Stefan chain, conservation, 4-connected clean-up): porous slices on every
+2D tile height, the storage modes, the full 1024^2 slice, and the y-invariant steady state, which
+D2Q5 and D2Q9 share exactly (the same D1Q3 x-marginal)."""
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+from paper_1809_01600_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_01600_amd import lbm_ms  # noqa: E402
+
+
+def _percolating(nx, ny, seed0, **kw):
+    seed = seed0
+    while True:
+        c = inputs.porous_2d(n=nx, ny=ny, seed=seed, **kw)
+        c.lattice = "D2Q5"
+        if oracle.label("D2Q5", c.mask())[1] > 0:
+            return c
+        seed += 1
+
+
+def _perm():
+    e, _ = lbm_ms.lattice_info(lbm_ms.D2Q5)
+    eo, _ = oracle.velocities("D2Q5")
+    return [eo.tolist().index(v) for v in e.tolist()]
+
+
+@pytest.mark.parametrize("ty", [4, 8, 16])
+def test_porous_slice_matches_oracle_on_every_tile(ty):
+    case = _percolating(96, 40, 200, tau_ref=3.0)
+    s = lbm_ms.Solver(case, precision="fp64", tile_y=ty)
+    o = oracle.Oracle(case)
+    assert np.array_equal(s.get_geometry(), o.solid)
+    s.init()
+    o.init_uniform()
+    s.step(60)
+    o.step(60)
+    err = float(np.max(np.abs(s.get_fields() - o.moments())))
+    fo, _, _, _ = o.collide()
+    errf = float(np.max(np.abs(s.get_populations() - fo[:, _perm()])))
+    print("D2Q5 tile %d: max |dX| %.3e, max |df*| %.3e" % (ty, err, errf))
+    assert err <= 1e-12 and errf <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("precision,shift,tol", [
+    ("fp32", lbm_ms.SHIFT_GLOBAL, 2e-6),
+    ("bf16", lbm_ms.SHIFT_GLOBAL, 2e-3),
+    ("fp32", lbm_ms.SHIFT_NODE, 2e-6),
+    ("bf16", lbm_ms.SHIFT_NODE, 2e-3),
+])
+def test_storage_modes_short_run(precision, shift, tol):
+    case = _percolating(96, 40, 210, tau_ref=5.0)
+    s = lbm_ms.Solver(case, precision=precision, shift_mode=shift)
+    o = oracle.Oracle(case)
+    s.init()
+    o.init_uniform()
+    s.step(200)
+    o.step(200)
+    err = float(np.max(np.abs(s.get_fields() - o.moments())))
+    print("D2Q5 %s shift %d: max |dX| after 200 steps = %.3e" % (precision, shift, err))
+    assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("precision,mode,tol", [("fp64", lbm_ms.LOCAL_FLUX, 1e-12),
+                                               ("fp32", lbm_ms.STOICH, 3e-6)])
+def test_full_size_slice_matches_oracle(precision, mode, tol):
+    """The 1024^2 porous slice of the benchmark on D2Q5, three steps from a random start.  FP32
+    runs with the stoichiometric ratio: from a random start the local flux-norm ratio of Eq. 24
+    amplifies FP32 rounding at a few nodes (max 8e-6 here, 2.4e-6 on D2Q9, while the 99.99th
+    percentile stays at 8e-8 on both), which would hide the lattice's own error."""
+    case = inputs.porous_2d()
+    case.lattice = "D2Q5"
+    o = oracle.Oracle(case, ms_mode=mode)
+    X0 = inputs.random_field(case.shape, seed=9, lo=0.2, hi=0.8)
+    o.init_field(X0)
+    o.step(3)
+    Xo = o.moments()
+    s = lbm_ms.Solver(case, precision=precision, ms_mode=mode)
+    s.init(X0)
+    s.step(3)
+    err = float(np.max(np.abs(s.get_fields() - Xo)))
+    print("D2Q5 1024^2 %s: max |dX| after 3 steps = %.3e" % (precision, err))
+    assert err <= tol
+    s.close()
+
+
+def test_y_invariant_steady_state_is_the_chain_and_equals_d2q9():
+    nx = 40
+    out = {}
+    for lat in ("D2Q5", "D2Q9"):
+        case = inputs.stefan_tube(nx=nx, ny=4, dx=0.1 / nx, tau_ref=5.0, j_A_cm2=0.5, lattice=lat)
+        s = lbm_ms.Solver(case, precision="fp64", ms_mode=lbm_ms.STOICH)
+        s.init()
+        s.converge(1e-15, 2_000_000, check_every=1000)
+        out[lat] = s.get_fields()[:2, 0]
+        s.close()
+    lp = oracle.lattice_params(case, case.ny)
+    chain = cf.discrete_chain_stoich(lp["Dl"], case.X_in, lp["Q"], nx)
+    err_chain = float(np.max(np.abs(out["D2Q5"] - chain[:, None, :])))
+    err_lat = float(np.max(np.abs(out["D2Q5"] - out["D2Q9"])))
+    print("D2Q5 steady: |X - chain| %.2e, |D2Q5 - D2Q9| %.2e" % (err_chain, err_lat))
+    assert err_chain <= 1e-10 and err_lat <= 1e-10
+
+
+def test_conserves_species_one_step():
+    case = _percolating(96, 40, 220, tau_ref=3.0)
+    s = lbm_ms.Solver(case, precision="fp64")
+    s.init(inputs.random_field(case.shape, seed=221, lo=0.2, hi=0.8))
+    inv, inflow, outflow = s.mass_balance()
+    s.step(1)
+    inv2, _, _ = s.mass_balance()
+    assert np.allclose(inv2 - inv, inflow - outflow, rtol=0, atol=1e-13 * np.max(inv))
+    s.close()
