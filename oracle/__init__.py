@@ -56,6 +56,7 @@ class _Params(ctypes.Structure):
         ("eps", ctypes.c_double),
         ("tau_min", ctypes.c_double), ("tau_max", ctypes.c_double),
         ("S", ctypes.c_double * 2), ("src_x0", ctypes.c_int),
+        ("trt", ctypes.c_int), ("lambda_trt", ctypes.c_double),
     ]
 
 
@@ -200,11 +201,18 @@ class Oracle:
         p.eps = default_eps(Q) if eps is None else eps
         p.tau_min, p.tau_max = tau_min, tau_max
         p.S[0], p.S[1], p.src_x0 = 0.0, 0.0, case.nx  # no volumetric source
+        p.trt, p.lambda_trt = 0, 0.25  # BGK unless set_trt
         self.p = p
         self.N = case.nx * case.ny * case.nz
         self.f = np.zeros((2, self.q) + case.shape)
         self.t = 0
         self.last = _Stats()
+
+    def set_trt(self, lam: Optional[float] = 0.25):
+        """Two-relaxation-time collision with (tau_even - 1/2)(tau - 1/2) = lam; None restores
+        the paper's BGK collision (Eq. 28)."""
+        self.p.trt = 0 if lam is None else 1
+        self.p.lambda_trt = 0.25 if lam is None else float(lam)
 
     def set_source(self, x_first: int, j_A_cm2: float):
         """Reaction spread uniformly over the fluid nodes of the columns x >= x_first (a functional

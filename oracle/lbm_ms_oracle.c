@@ -48,6 +48,8 @@ typedef struct {
     double tau_min, tau_max;
     double S[2];          /* source per fluid node and step of the columns x >= src_x0 (Eq. 27) */
     int src_x0;
+    int trt;              /* 1: two-relaxation-time collision instead of BGK */
+    double lambda_trt;    /* TRT: (tau_even - 1/2)(tau - 1/2), tau from Eq. 25 */
 } orc_params;
 
 typedef struct {
@@ -308,13 +310,24 @@ static int collide_all(const orc_params* p, const orc_lattice* L, const uint8_t*
                     for (int s = 0; s < 2; ++s)
                         for (int d = 0; d < 3; ++d) J_out[((long)s * 3 + d) * N + n] = J[s][d];
 
-                /* step 6: BGK collision toward w_a X_s, and the source term w_a S_s (Eq. 27) */
-                for (int s = 0; s < 2; ++s)
+                /* step 6: BGK collision toward w_a X_s, and the source term w_a S_s (Eq. 27).
+                 * TRT variant: the odd part of each link pair, (f_a - f_abar) / 2, relaxes with
+                 * tau (it carries the flux, so tau keeps setting D through Eq. 25); the even part,
+                 * (f_a + f_abar) / 2 - w_a X, relaxes with tau_even = 1/2 + Lambda / (tau - 1/2). */
+                for (int s = 0; s < 2; ++s) {
+                    const double tau_even = 0.5 + p->lambda_trt / (tau[s] - 0.5);
                     for (int a = 0; a < q; ++a) {
                         long k = ((long)s * q + a) * N + n;
-                        fstar[k] = f[k] - (f[k] - L->w[a] * Xn[s]) / tau[s];
+                        if (p->trt) {
+                            long kb = ((long)s * q + L->opp[a]) * N + n;
+                            const double fe = 0.5 * (f[k] + f[kb]), fo = 0.5 * (f[k] - f[kb]);
+                            fstar[k] = f[k] - (fe - L->w[a] * Xn[s]) / tau_even - fo / tau[s];
+                        } else {
+                            fstar[k] = f[k] - (f[k] - L->w[a] * Xn[s]) / tau[s];
+                        }
                         if (x >= p->src_x0) fstar[k] += L->w[a] * p->S[s];
                     }
+                }
             }
     free(X);
     if (clamp_hits) *clamp_hits = hits;

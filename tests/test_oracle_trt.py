@@ -1,0 +1,72 @@
+"""Pins of the oracle's two-relaxation-time collision (no GPU).  TRT splits each link pair into an
+odd part, relaxed with the Eq. 25 tau (it carries the flux, so D is unchanged), and an even part,
+relaxed with tau_even = 1/2 + Lambda / (tau - 1/2).  Pinned against: the reduction to BGK when
+tau_even = tau; conservation in a closed box; and the property TRT exists for, a porous steady
+state independent of tau_ref at fixed Lambda, while BGK's moves with tau_ref."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01600_amd import inputs
+from test_oracle import run_to_steady
+
+
+def _percolating(lat, shape, seed0, **kw):
+    nz, ny, nx = shape
+    seed = seed0
+    while True:
+        c = inputs.random_small(nx, ny, nz, lat, seed=seed, **kw)
+        if oracle.label(lat, c.mask())[1] > 0:
+            return c
+        seed += 1
+
+
+def test_trt_reduces_to_bgk_when_the_even_rate_equals_the_odd_one():
+    """Binary feed, stoichiometric fluxes: tau = tau_ref at every node, so Lambda = (tau - 1/2)^2
+    gives tau_even = tau and TRT must reproduce BGK."""
+    tau = 1.7
+    case = dataclasses.replace(_percolating("D2Q9", (1, 12, 30), 400, solid_frac=0.2, tau_ref=tau),
+                               X_in=(0.5, 0.5, 0.0))
+    X0 = inputs.random_field(case.shape, seed=401, lo=0.2, hi=0.8)
+    X0[1] = 1.0 - X0[0]
+    X0[2] = 0.0
+    out = []
+    for trt in (False, True):
+        o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+        if trt:
+            o.set_trt((tau - 0.5) ** 2)
+        o.init_field(X0)
+        o.step(50)
+        out.append(o.moments())
+    assert np.max(np.abs(out[0] - out[1])) < 1e-14
+
+
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17))])
+def test_trt_closed_box_conserves(lat, shape):
+    case = inputs.random_small(shape[2], shape[1], shape[0], lat, seed=410, solid_frac=0.2, j_A_cm2=0.0)
+    o = oracle.Oracle(case, ms_mode=oracle.STOICH, inlet_wall=True)
+    o.set_trt(0.25)
+    o.init_field(inputs.random_field(case.shape, seed=411))
+    inv0 = o.inventory()
+    o.step(150)
+    assert np.allclose(o.inventory(), inv0, rtol=1e-13, atol=0)
+
+
+def test_trt_porous_steady_state_does_not_depend_on_tau_ref():
+    base = _percolating("D2Q9", (1, 16, 40), 300, solid_frac=0.25, tau_ref=2.0, j_A_cm2=0.5)
+    diff = {}
+    for trt in (False, True):
+        res = []
+        for tau_ref in (1.5, 4.0):
+            o = oracle.Oracle(dataclasses.replace(base, tau_ref=tau_ref), ms_mode=oracle.STOICH)
+            if trt:
+                o.set_trt(0.25)
+            o.init_uniform()
+            X, _ = run_to_steady(o, window=2000, tol=1e-15)
+            res.append(X)
+        diff[trt] = float(np.max(np.abs(res[0] - res[1])))
+    assert diff[True] < 1e-10, diff
+    assert diff[False] > 1e-5, diff  # BGK's bounce-back walls move with tau
