@@ -40,7 +40,7 @@ LOCAL_FLUX = 0
 STOICH = 1
 
 
-LATTICE_CODES = {"D2Q9": 0, "D3Q19": 1, "D2Q5": 2}
+LATTICE_CODES = {"D2Q9": 0, "D3Q19": 1, "D2Q5": 2, "D3Q7": 3}
 
 
 class _Params(ctypes.Structure):

@@ -36,7 +36,7 @@
 #include <string.h>
 
 typedef struct {
-    int lattice;          /* 0: D2Q9, 1: D3Q19, 2: D2Q5 */
+    int lattice;          /* 0: D2Q9, 1: D3Q19, 2: D2Q5, 3: D3Q7 */
     int nx, ny, nz;       /* nz = 1 for D2Q9 */
     double Dl[3][3];      /* lattice binary diffusivities D*_ij = D_ij dt / dx^2 (symmetric) */
     double X_in[2];       /* inlet mole fractions of the evolved species */
@@ -83,6 +83,19 @@ static void build_lattice(int lattice, orc_lattice* L)
             L->e[a][1] = ey[a];
             L->e[a][2] = 0;
             L->w[a] = (a == 0) ? 1.0 / 3.0 : 1.0 / 6.0;
+        }
+    } else if (lattice == 3) {
+        /* D3Q7: rest and the six axis links.  Sec. 3.1 fixes c_s^2 = 1/3 (so tau = 3 D* + 1/2,
+         * Eq. 25); sum_a w_a e_a e_a = 2 w_axis I then needs w_axis = 1/6, and unit mass leaves
+         * the rest link a weight of 0 */
+        static const int ex[7] = {0, 1, -1, 0, 0, 0, 0}, ey[7] = {0, 0, 0, 1, -1, 0, 0},
+                         ez[7] = {0, 0, 0, 0, 0, 1, -1};
+        L->q = 7;
+        for (int a = 0; a < 7; ++a) {
+            L->e[a][0] = ex[a];
+            L->e[a][1] = ey[a];
+            L->e[a][2] = ez[a];
+            L->w[a] = (a == 0) ? 0.0 : 1.0 / 6.0;
         }
     } else if (lattice == 0) {
         L->q = 9;
@@ -214,7 +227,7 @@ static int collide_all(const orc_params* p, const orc_lattice* L, const uint8_t*
 {
     const long N = (long)p->nx * p->ny * p->nz;
     const int q = L->q;
-    const int dims = (p->lattice == 1) ? 3 : 2;
+    const int dims = (p->lattice == 1 || p->lattice == 3) ? 3 : 2;
     double* X = (double*)malloc(sizeof(double) * 3 * N);
     if (!X) return -8;
     orc_moments(p, solid, f, X);

@@ -63,10 +63,10 @@ def test_constants_are_the_papers():
     assert c.n_electrons == vals["n_electrons"]
 
 
-@pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19), ("D2Q5", 5)])
+@pytest.mark.parametrize("lat,q", [("D2Q9", 9), ("D3Q19", 19), ("D2Q5", 5), ("D3Q7", 7)])
 def test_velocity_set_isotropy(lat, q):
     e, w = oracle.velocities(lat)
-    d = 3 if lat == "D3Q19" else 2
+    d = 3 if lat.startswith("D3") else 2
     assert len(w) == q
     assert abs(w.sum() - 1.0) < 1e-15
     assert np.allclose((w[:, None] * e).sum(0), 0.0, atol=1e-16)
@@ -91,6 +91,8 @@ def _label_reference(lattice, solid):
     elif lattice == "D2Q5":  # axis links only: 4-connectivity
         lab, n = ndimage.label(fluid[0], structure=ndimage.generate_binary_structure(2, 1))
         lab = lab[None]
+    elif lattice == "D3Q7":  # axis links only: 6-connectivity
+        lab, n = ndimage.label(fluid, structure=ndimage.generate_binary_structure(3, 1))
     else:
         lab, n = ndimage.label(fluid, structure=ndimage.generate_binary_structure(3, 2))
     parent = list(range(n + 1))
@@ -132,10 +134,11 @@ def _label_reference(lattice, solid):
 
 @pytest.mark.parametrize("lat,shape,seed", [("D2Q9", (1, 40, 30), 1), ("D2Q9", (1, 25, 33), 2),
                                             ("D3Q19", (9, 11, 13), 3), ("D2Q5", (1, 40, 30), 4),
-                                            ("D2Q5", (1, 25, 33), 5)])
+                                            ("D2Q5", (1, 25, 33), 5), ("D3Q7", (9, 11, 13), 6),
+                                            ("D3Q7", (7, 10, 12), 7)])
 def test_label_matches_scipy(lat, shape, seed):
     rng = np.random.default_rng(seed)
-    frac = {"D2Q9": 0.55, "D2Q5": 0.35, "D3Q19": 0.7}[lat]
+    frac = {"D2Q9": 0.55, "D2Q5": 0.35, "D3Q19": 0.7, "D3Q7": 0.6}[lat]
     solid = (rng.random(shape) < frac).astype(np.uint8)
     got, n_open = oracle.label(lat, solid)
     ref = _label_reference(lat, solid)
@@ -197,10 +200,13 @@ def test_exact_variance_d2q9(tau, lat):
         assert abs(vy - cf.exact_variance(var0y, tau, t)) < 1e-10 * vy
 
 
-def test_exact_variance_d3q19():
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q7"])
+def test_exact_variance_d3q19(lat):
+    """The 3D sets have the D1Q3 marginal on every axis (weights 1/6, 2/3, 1/6), so the per-axis
+    second moment of a pulse follows the same exact relation."""
     n = 40
     tau = 1.0
-    case = inputs.stefan_tube(nx=n, ny=n, nz=n, lattice="D3Q19", tau_ref=tau,
+    case = inputs.stefan_tube(nx=n, ny=n, nz=n, lattice=lat, tau_ref=tau,
                               X_in=(0.5, 0.5, 0.0), j_A_cm2=0.0)
     o = oracle.Oracle(case, ms_mode=oracle.STOICH)
     zz, yy, xx = np.meshgrid(*(np.arange(n) - n / 2,) * 3, indexing="ij")
@@ -210,21 +216,22 @@ def test_exact_variance_d3q19():
     X0[0] += bump
     X0[1] -= bump
     o.init_field(X0)
-    dX = o.moments()[0] - 0.5
+    # deviations from the far corner's own value (see the 2D test)
+    dX = o.moments()[0] - o.moments()[0, 0, 0, 0]
     M0 = dX.sum()
     v0 = [(dX * c ** 2).sum() / M0 for c in (xx, yy, zz)]
     o.step(12)
-    dX = o.moments()[0] - 0.5
+    dX = o.moments()[0] - o.moments()[0, 0, 0, 0]
     for c, v in zip((xx, yy, zz), v0):
         got = (dX * c ** 2).sum() / dX.sum()
         assert abs(got - cf.exact_variance(v, tau, 12)) < 1e-10 * got
 
 
-@pytest.mark.parametrize("lat", ["D2Q9", "D2Q5"])
+@pytest.mark.parametrize("lat", ["D2Q9", "D2Q5", "D3Q7"])
 def test_stefan_chain_stoichiometric(lat):
     """Strongly coupled ternary tube (long tube, X_1 falls from 0.6 to ~0.3): the time-stepped
-    steady state equals the exact discrete chain solved by Newton's method.  D2Q5 has the same
-    D1Q3 x-marginal as D2Q9, so its y-uniform steady state is the same chain."""
+    steady state equals the exact discrete chain solved by Newton's method.  D2Q5 and D3Q7 have
+    the same D1Q3 x-marginal as D2Q9, so their y-uniform steady state is the same chain."""
     nx = 40
     case = inputs.stefan_tube(nx=nx, ny=1, dx=0.1 / nx, tau_ref=5.0, j_A_cm2=0.5, lattice=lat)
     o = oracle.Oracle(case, ms_mode=oracle.STOICH)
@@ -279,7 +286,8 @@ def test_stefan_continuum_second_order(mode):
 # conservation
 # ----------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17))])
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17)),
+                                       ("D3Q7", (6, 7, 9))])
 def test_closed_box_conserves(lat, shape):
     nz, ny, nx = shape
     case = inputs.random_small(nx, ny, nz, lat, seed=11, solid_frac=0.2, j_A_cm2=0.0)
@@ -293,7 +301,8 @@ def test_closed_box_conserves(lat, shape):
 
 @pytest.mark.parametrize("lat,shape,mode", [("D2Q9", (1, 16, 20), oracle.LOCAL_FLUX),
                                             ("D3Q19", (5, 6, 10), oracle.STOICH),
-                                            ("D2Q5", (1, 16, 20), oracle.LOCAL_FLUX)])
+                                            ("D2Q5", (1, 16, 20), oracle.LOCAL_FLUX),
+                                            ("D3Q7", (5, 6, 10), oracle.LOCAL_FLUX)])
 def test_open_mass_balance(lat, shape, mode):
     """Every step: inventory change = inflow - outflow, and the outflow is Q_s per open node."""
     nz, ny, nx = shape

@@ -44,7 +44,8 @@ def test_trt_reduces_to_bgk_when_the_even_rate_equals_the_odd_one():
     assert np.max(np.abs(out[0] - out[1])) < 1e-14
 
 
-@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17))])
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 14, 17)), ("D3Q19", (6, 7, 9)), ("D2Q5", (1, 14, 17)),
+                                       ("D3Q7", (6, 7, 9))])
 def test_trt_closed_box_conserves(lat, shape):
     case = inputs.random_small(shape[2], shape[1], shape[0], lat, seed=410, solid_frac=0.2, j_A_cm2=0.0)
     o = oracle.Oracle(case, ms_mode=oracle.STOICH, inlet_wall=True)
