@@ -67,6 +67,12 @@ enum { LBM_MS_LOCAL_FLUX = 0, LBM_MS_STOICH = 1 };
 /* x = 0 face: Dirichlet anti-bounce-back (Eq. 36) or a bounce-back wall (closed box) */
 enum { LBM_MS_INLET_DIRICHLET = 0, LBM_MS_INLET_WALL = 1 };
 
+/* Collision: the paper's BGK (Eq. 28), or two relaxation times (TRT): the odd part of each link
+ * pair relaxes with the Eq. 25 tau, which keeps setting the diffusivity, and the even part with
+ * tau_even = 1/2 + Lambda / (tau - 1/2).  With Lambda fixed, steady states in resolved porous
+ * media no longer depend on tau_ref (BGK's bounce-back walls move with tau). */
+enum { LBM_MS_BGK = 0, LBM_MS_TRT = 1 };
+
 typedef struct {
     int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; not for batches) or LBM_MS_D3Q19 */
     int nx, ny, nz;       /* nodes; nz must be 1 for D2Q9; nx >= 2 */
@@ -90,6 +96,8 @@ typedef struct {
     int tile_y;           /* launch shape (0 = default); see lbm_ms_tile_options */
     int chunk_z;          /* D3Q19 planes per workgroup (0 = default) */
     void* stream;         /* hipStream_t */
+    int collision;        /* LBM_MS_BGK (0, the paper's) or LBM_MS_TRT */
+    double trt_lambda;    /* TRT Lambda = (tau_even - 1/2)(tau - 1/2); <= 0 selects 1/4 */
 } lbm_ms_params;
 
 typedef struct {

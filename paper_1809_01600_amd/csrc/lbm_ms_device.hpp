@@ -194,6 +194,8 @@ struct StepArgs {
     int inlet_wall;           // 1: x = 0 face is a bounce-back wall
     double S0, S1;            // volumetric source per fluid node and step (Eq. 27) ...
     int src_x0;               // ... on the columns x >= src_x0 (nx: none)
+    int trt;                  // 1: two-relaxation-time collision
+    double trt_lambda;        // (tau_even - 1/2)(tau - 1/2)
 };
 
 // Map the hardware block index to a tile so that each of the 8 XCDs (blocks are dealt to XCDs
@@ -573,46 +575,79 @@ __device__ inline void collide_store(const StepArgs& a, int n,
     const unsigned plane = (unsigned)a.P * ES;
     const unsigned spec = (unsigned)L::Q * plane;
     const unsigned base = (unsigned)n * ES;
-    if constexpr (NS) {
-        const float k0 = (float)(1.0 - om0), k1 = (float)(1.0 - om1);
-        using AT = typename std::conditional<P == P_F32, double, float>::type;
-        AT sh0 = 0, sh1 = 0;
-#pragma unroll
-        for (int k = 0; k < L::Q; ++k) {
-            const raw r0 = C::enc(k0 * f[0][k], 0.f);
-            const raw r1 = C::enc(k1 * f[1][k], 0.f);
-            sh0 += (AT)C::dec(r0, 0.f);
-            sh1 += (AT)C::dec(r1, 0.f);
-            const unsigned off = base + (unsigned)k * plane;
-            gstore<raw>(fout, off, r0);
-            gstore<raw>(fout, off + spec, r1);
-        }
-        gstore<double>(a.xout, (unsigned)n * 8u, X0 + s0 - (double)sh0);
-        gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 + s1 - (double)sh1);
-        return;
+    // TRT: the odd part of a link pair relaxes with omega (it carries the flux, so Eq. 25 still
+    // sets D); the even part with omega_e = 1 / (1/2 + Lambda / (1/omega - 1/2))
+    double oe0 = om0, oe1 = om1;
+    if (a.trt) {
+        const double h0 = 1.0 - 0.5 * om0, h1 = 1.0 - 0.5 * om1;
+        oe0 = h0 * rcp64(0.5 * h0 + a.trt_lambda * om0);
+        oe1 = h1 * rcp64(0.5 * h1 + a.trt_lambda * om1);
     }
-    if (s0 != 0.0 || s1 != 0.0) {  // only on the reaction layer
-        X0 += s0 * rcp64(om0);
-        X1 += s1 * rcp64(om1);
-    }
-    const CT o0 = (CT)om0, o1 = (CT)om1;
-    const CT x0 = (CT)X0, x1 = (CT)X1;
-    const float c0 = (float)a.c0, c1 = (float)a.c1;
+    // a workgroup-uniform branch: the BGK loops carry no TRT terms
+    auto store = [&](auto trt_tag) {
+        constexpr bool TRT = decltype(trt_tag)::value;
+        if constexpr (NS) {
+            const float k0 = (float)(1.0 - om0), k1 = (float)(1.0 - om1);
+            const float d0 = (float)(0.5 * (om0 - oe0)), d1 = (float)(0.5 * (om1 - oe1));
+            using AT = typename std::conditional<P == P_F32, double, float>::type;
+            AT sh0 = 0, sh1 = 0;
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-        const CT wk = wgt<L, CT>(k);
-        const CT v0 = f[0][k] + o0 * (wk * x0 - f[0][k]);
-        const CT v1 = f[1][k] + o1 * (wk * x1 - f[1][k]);
-        const unsigned off = base + (unsigned)k * plane;
-        if constexpr (C::shifted) {
-            const float wf = L::wf[k];
-            gstore<raw>(fout, off, C::enc(v0, wf * c0));
-            gstore<raw>(fout, off + spec, C::enc(v1, wf * c1));
+            for (int k = 0; k < L::Q; ++k) {
+                // TRT: h = g - omega_e (g + g_bar) / 2 - omega (g - g_bar) / 2
+                //        = (1 - omega) g + d (g + g_bar),  d = (omega - omega_e) / 2
+                float h0 = k0 * f[0][k], h1 = k1 * f[1][k];
+                if constexpr (TRT) {
+                    const int o = L::opp[k];
+                    h0 += d0 * (f[0][k] + f[0][o]);
+                    h1 += d1 * (f[1][k] + f[1][o]);
+                }
+                const raw r0 = C::enc(h0, 0.f);
+                const raw r1 = C::enc(h1, 0.f);
+                sh0 += (AT)C::dec(r0, 0.f);
+                sh1 += (AT)C::dec(r1, 0.f);
+                const unsigned off = base + (unsigned)k * plane;
+                gstore<raw>(fout, off, r0);
+                gstore<raw>(fout, off + spec, r1);
+            }
+            gstore<double>(a.xout, (unsigned)n * 8u, X0 + s0 - (double)sh0);
+            gstore<double>(a.xout, (unsigned)n * 8u + (unsigned)a.NF * 8u, X1 + s1 - (double)sh1);
         } else {
-            gstore<raw>(fout, off, C::enc(v0, CT(0)));
-            gstore<raw>(fout, off + spec, C::enc(v1, CT(0)));
+            double Y0 = X0, Y1 = X1;
+            if (s0 != 0.0 || s1 != 0.0) {  // only on the reaction layer; the source is even
+                Y0 += s0 * rcp64(oe0);
+                Y1 += s1 * rcp64(oe1);
+            }
+            const CT o0 = (CT)om0, o1 = (CT)om1;
+            const CT x0 = (CT)Y0, x1 = (CT)Y1;
+            const CT d0 = (CT)(0.5 * (om0 - oe0)), d1 = (CT)(0.5 * (om1 - oe1));
+            const float c0 = (float)a.c0, c1 = (float)a.c1;
+#pragma unroll
+            for (int k = 0; k < L::Q; ++k) {
+                const CT wk = wgt<L, CT>(k);
+                CT v0 = f[0][k] + o0 * (wk * x0 - f[0][k]);
+                CT v1 = f[1][k] + o1 * (wk * x1 - f[1][k]);
+                if constexpr (TRT) {
+                    // f - omega_e (f_even - w x) - omega f_odd = BGK + d (f + f_bar - 2 w x)
+                    const int o = L::opp[k];
+                    v0 += d0 * (f[0][k] + f[0][o] - (CT)2 * wk * x0);
+                    v1 += d1 * (f[1][k] + f[1][o] - (CT)2 * wk * x1);
+                }
+                const unsigned off = base + (unsigned)k * plane;
+                if constexpr (C::shifted) {
+                    const float wf = L::wf[k];
+                    gstore<raw>(fout, off, C::enc(v0, wf * c0));
+                    gstore<raw>(fout, off + spec, C::enc(v1, wf * c1));
+                } else {
+                    gstore<raw>(fout, off, C::enc(v0, CT(0)));
+                    gstore<raw>(fout, off + spec, C::enc(v1, CT(0)));
+                }
+            }
         }
-    }
+    };
+    if (a.trt)
+        store(std::true_type{});
+    else
+        store(std::false_type{});
 }
 
 }  // namespace lbmms

@@ -77,6 +77,8 @@ bool valid_params(const lbm_ms_params* p, std::string* why)
     if (p->ms_mode != LBM_MS_LOCAL_FLUX && p->ms_mode != LBM_MS_STOICH) return fail("unknown ms_mode");
     if (p->inlet_mode != LBM_MS_INLET_DIRICHLET && p->inlet_mode != LBM_MS_INLET_WALL)
         return fail("unknown inlet mode");
+    if (p->collision != LBM_MS_BGK && p->collision != LBM_MS_TRT) return fail("unknown collision");
+    if (!std::isfinite(p->trt_lambda)) return fail("trt_lambda must be finite");
     if (!(p->T > 0) || !(p->p > 0) || !(p->dx > 0)) return fail("T, p, dx must be positive");
     if (!(p->tau_ref > 0.5)) return fail("tau_ref must exceed 1/2");
     const double d12 = p->D[1], d13 = p->D[2], d23 = p->D[5];
@@ -217,6 +219,8 @@ struct lbm_ms_s {
         a.S0 = S[0];
         a.S1 = S[1];
         a.src_x0 = src_x0 < p.nx ? src_x0 : p.nx;
+        a.trt = p.collision == LBM_MS_TRT ? 1 : 0;
+        a.trt_lambda = p.trt_lambda > 0 ? p.trt_lambda : 0.25;
         return a;
     }
     int nblocks_step() const

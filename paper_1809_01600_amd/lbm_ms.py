@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_ms.so")
 
 D2Q9, D3Q19, D2Q5 = 0, 1, 2
+BGK, TRT = 0, 1
+COLLISIONS = {"bgk": BGK, "trt": TRT}
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D2Q5": D2Q5}
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5}
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
@@ -51,6 +53,8 @@ class lbm_ms_params(ctypes.Structure):
         ("tile_y", ctypes.c_int),
         ("chunk_z", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("collision", ctypes.c_int),
+        ("trt_lambda", ctypes.c_double),
     ]
 
 
@@ -211,7 +215,8 @@ def tile_options(lattice: int, precision: int = FP32):
 def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
                 ms_mode: int = LOCAL_FLUX, inlet_mode: int = INLET_DIRICHLET,
                 eps_flux: float = -1.0, tau_min: float = 0.0, tau_max: float = 0.0,
-                tile_y: int = 0, chunk_z: int = 0, stream: Optional[int] = None) -> lbm_ms_params:
+                tile_y: int = 0, chunk_z: int = 0, stream: Optional[int] = None,
+                collision="bgk", trt_lambda: float = 0.0) -> lbm_ms_params:
     """Marshal a physical problem description (inputs.Case) into lbm_ms_params."""
     p = lbm_ms_params()
     p.lattice = LATTICES[case.lattice]
@@ -233,6 +238,8 @@ def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
     p.tau_min, p.tau_max = tau_min, tau_max
     p.tile_y, p.chunk_z = tile_y, chunk_z
     p.stream = stream
+    p.collision = COLLISIONS[collision] if isinstance(collision, str) else int(collision)
+    p.trt_lambda = trt_lambda
     return p
 
 
@@ -241,7 +248,8 @@ class Solver:
 
     def __init__(self, case, precision="fp64", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
                  inlet_mode=INLET_DIRICHLET, eps_flux=-1.0, tau_min=0.0, tau_max=0.0,
-                 tile_y=0, chunk_z=0, device="cuda", set_geometry=True, set_bc=True):
+                 tile_y=0, chunk_z=0, device="cuda", set_geometry=True, set_bc=True,
+                 collision="bgk", trt_lambda=0.0):
         import torch
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -249,7 +257,8 @@ class Solver:
         self.torch_device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.torch_device)
         self.params = make_params(case, precision, shift_mode, ms_mode, inlet_mode, eps_flux,
-                                  tau_min, tau_max, tile_y, chunk_z, self.stream.cuda_stream)
+                                  tau_min, tau_max, tile_y, chunk_z, self.stream.cuda_stream,
+                                  collision, trt_lambda)
         nbytes = lib().lbm_ms_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise LbmMsError(E_ARG, lib().lbm_ms_last_error(None).decode())
@@ -423,7 +432,7 @@ class Batch:
     """Many D2Q9 problems advanced by one launch per step (see lbm_ms_batch_* in lbm_ms.h)."""
 
     def __init__(self, cases, precision="fp32", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
-                 tile_y=0, eps_flux=-1.0, device="cuda"):
+                 tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0):
         import torch
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -438,7 +447,7 @@ class Batch:
             raise ValueError("batched solves are two-dimensional (D2Q9)")
         self.stream = torch.cuda.current_stream(torch.device(device))
         self.params = make_params(c0, precision, shift_mode, ms_mode, INLET_DIRICHLET, eps_flux,
-                                  0.0, 0.0, tile_y, 0, self.stream.cuda_stream)
+                                  0.0, 0.0, tile_y, 0, self.stream.cuda_stream, collision, trt_lambda)
         n = len(self.cases)
         self._masks = [np.ascontiguousarray(c.mask(), dtype=np.uint8).reshape(-1) for c in self.cases]
         self.desc = (lbm_ms_instance_desc * n)()

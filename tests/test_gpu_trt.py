@@ -1,0 +1,91 @@
+"""The two-relaxation-time collision on the GPU through the C ABI, against the oracle's (pinned on
+the CPU: reduction to BGK, conservation, tau_ref-independent porous steady states): short runs
+from a random start on every lattice and storage family, with and without the volumetric source,
+the batch, and the tau_ref independence of a converged porous steady state on the GPU itself."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_01600_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_01600_amd import lbm_ms  # noqa: E402
+
+
+def _percolating(lat, shape, seed0, **kw):
+    nz, ny, nx = shape
+    seed = seed0
+    while True:
+        c = inputs.random_small(nx, ny, nz, lat, seed=seed, solid_frac=0.2, **kw)
+        if oracle.label(lat, c.mask())[1] > 0:
+            return c
+        seed += 1
+
+
+@pytest.mark.parametrize("lat,shape,precision,shift,tol,source", [
+    ("D2Q9", (1, 40, 96), "fp64", lbm_ms.SHIFT_GLOBAL, 1e-12, False),
+    ("D2Q5", (1, 40, 96), "fp64", lbm_ms.SHIFT_GLOBAL, 1e-12, False),
+    ("D3Q19", (9, 11, 40), "fp64", lbm_ms.SHIFT_GLOBAL, 1e-12, False),
+    ("D2Q9", (1, 40, 96), "fp64", lbm_ms.SHIFT_GLOBAL, 1e-12, True),
+    ("D2Q9", (1, 40, 96), "fp32", lbm_ms.SHIFT_GLOBAL, 2e-6, False),
+    ("D2Q9", (1, 40, 96), "bf16", lbm_ms.SHIFT_NODE, 2e-3, False),
+    ("D3Q19", (9, 11, 40), "fp32", lbm_ms.SHIFT_NODE, 2e-6, True),
+])
+def test_trt_short_run_matches_oracle(lat, shape, precision, shift, tol, source):
+    case = _percolating(lat, shape, 500, j_A_cm2=0.5, tau_ref=5.0)
+    s = lbm_ms.Solver(case, precision=precision, shift_mode=shift, ms_mode=lbm_ms.STOICH,
+                      collision="trt", trt_lambda=0.25)
+    o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+    o.set_trt(0.25)
+    if source:
+        s.set_source(shape[2] - 10, 1.0e4)
+        o.set_source(shape[2] - 10, 1.0)
+    X0 = inputs.random_field(case.shape, seed=501, lo=0.2, hi=0.8)
+    s.init(X0)
+    o.init_field(X0)
+    s.step(100)
+    o.step(100)
+    err = float(np.max(np.abs(s.get_fields() - o.moments())))
+    print("TRT %s %s shift %d source %s: max |dX| after 100 steps = %.3e" % (lat, precision, shift, source, err))
+    assert err <= tol
+    s.close()
+
+
+def test_trt_batch_matches_oracle():
+    cases = [_percolating("D2Q9", (1, 33, 70), 520, j_A_cm2=j, tau_ref=3.0) for j in (0.4, 1.2)]
+    cases[1] = dataclasses.replace(cases[1], tau_ref=3.0)
+    b = lbm_ms.Batch(cases, precision="fp64", ms_mode=lbm_ms.STOICH, collision="trt")
+    b.init()
+    b.step(120)
+    for k, c in enumerate(cases):
+        o = oracle.Oracle(c, ms_mode=oracle.STOICH)
+        o.set_trt(0.25)
+        o.init_uniform()
+        o.step(120)
+        assert np.max(np.abs(b.instance(k).get_fields() - o.moments())) < 1e-12, k
+    b.close()
+
+
+def test_trt_porous_steady_state_independent_of_tau_ref_on_gpu():
+    base = _percolating("D2Q9", (1, 24, 64), 530, j_A_cm2=0.5, tau_ref=2.0)
+    out = {}
+    for coll in ("bgk", "trt"):
+        res = []
+        for tau_ref in (1.5, 4.0):
+            s = lbm_ms.Solver(dataclasses.replace(base, tau_ref=tau_ref), precision="fp64",
+                              ms_mode=lbm_ms.STOICH, collision=coll)
+            s.init()
+            s.converge(1e-15, 3_000_000, check_every=1000)
+            res.append(s.get_fields())
+            s.close()
+        out[coll] = float(np.max(np.abs(res[0] - res[1])))
+    print("steady state, tau_ref 1.5 vs 4: BGK %.2e, TRT %.2e" % (out["bgk"], out["trt"]))
+    assert out["trt"] < 1e-10 and out["bgk"] > 1e-5
