@@ -32,7 +32,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16"): 72,
                   ("D2Q9", "bf16"): 72, ("D3Q19", "fp64"): 608, ("D3Q19", "fp32"): 304,
                   ("D3Q19", "fp16"): 152, ("D3Q19", "bf16"): 152, ("D2Q5", "fp64"): 160,
-                  ("D2Q5", "fp32"): 80, ("D2Q5", "fp16"): 40, ("D2Q5", "bf16"): 40}
+                  ("D2Q5", "fp32"): 80, ("D2Q5", "fp16"): 40, ("D2Q5", "bf16"): 40,
+                  ("D3Q7", "fp64"): 224, ("D3Q7", "fp32"): 112, ("D3Q7", "fp16"): 56,
+                  ("D3Q7", "bf16"): 56}
+# the lattice each workload is defined on, and the alternative velocity set it accepts
+WORKLOAD_LATTICES = {"porous_2d": ("D2Q9", "D2Q5"), "porous_3d": ("D3Q19", "D3Q7"),
+                     "batch_2d": ("D2Q9",)}
 NODE_SHIFT_BYTES = 2 * 8 * 2
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
                   "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
@@ -71,7 +76,7 @@ def cpu_baseline(case, steps: int):
     import numpy as np
     import oracle
     sample = case
-    if case.lattice == "D3Q19" and case.nz > 32:
+    if case.nz > 32:
         sample = dataclasses.replace(case, nz=32, solid=np.ascontiguousarray(case.mask()[:32]))
     o = oracle.Oracle(sample)
     o.init_uniform()
@@ -98,8 +103,9 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--shift", default="global", choices=["global", "node"])
     ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
-    ap.add_argument("--lattice", default="d2q9", choices=["d2q9", "d2q5"],
-                    help="velocity set of the porous_2d slice")
+    ap.add_argument("--lattice", default="", choices=["", "d2q9", "d2q5", "d3q19", "d3q7"],
+                    help="velocity set: d2q9 (default) or d2q5 for porous_2d, d3q19 (default) or "
+                         "d3q7 for porous_3d")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--chunk-z", type=int, default=0)
@@ -107,6 +113,10 @@ def main(argv=None):
                     help="oracle steps of the CPU baseline (default 40 in 2D, 6 in 3D)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
+    lattices = WORKLOAD_LATTICES[args.workload]
+    if args.lattice and args.lattice.upper() not in lattices:
+        ap.error("--workload %s takes --lattice %s" % (args.workload, " or ".join(l.lower() for l in lattices)))
+    args.lattice = args.lattice.upper() or lattices[0]
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver shards nothing across GPUs "
@@ -122,13 +132,14 @@ def main(argv=None):
         return run_batch(args)
     if args.workload == "porous_2d":
         case = inputs.porous_2d()
-        case.lattice = args.lattice.upper()
+        case.lattice = args.lattice
         desc = ("porous anode slice %s 1024x1024, overlapping disks r~U[4,12], void fraction "
                 "0.40, seed 2, X_in~Dirichlet(6,3,1), j=1.0 A/cm^2" % case.lattice)
     else:
         case = inputs.porous_3d()
-        desc = ("porous anode block D3Q19 256^3, overlapping spheres r~U[3,8], void fraction "
-                "~U[0.35,0.50], seed 3, X_in=(0.6,0.3,0.1), j=1.0 A/cm^2")
+        case.lattice = args.lattice
+        desc = ("porous anode block %s 256^3, overlapping spheres r~U[3,8], void fraction "
+                "~U[0.35,0.50], seed 3, X_in=(0.6,0.3,0.1), j=1.0 A/cm^2" % case.lattice)
     shift = lbm_ms.SHIFT_NODE if args.shift == "node" else lbm_ms.SHIFT_GLOBAL
     s = lbm_ms.Solver(case, precision=args.precision, shift_mode=shift, tile_y=args.tile_y,
                       chunk_z=args.chunk_z)
@@ -159,7 +170,8 @@ def main(argv=None):
     if shift == lbm_ms.SHIFT_NODE:  # FP64 node reference per evolved species, read and written
         bytes_per_launch += NODE_SHIFT_BYTES * n_fluid
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    wl_key = "%s%s_%s_%s" % (args.workload, "_d2q5" if case.lattice == "D2Q5" else "", args.precision, args.shift)
+    alt = "" if case.lattice == lattices[0] else "_" + case.lattice.lower()
+    wl_key = "%s%s_%s_%s" % (args.workload, alt, args.precision, args.shift)
     traffic = measured_traffic(wl_key, kernel_hash())
 
     ms_per_step = elapsed * 1e3 / K
@@ -199,13 +211,13 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step3d" if case.lattice == "D3Q19" else "k_step2d",
+            "kernel": "k_step3d" if case.nz > 1 else "k_step2d",
             "kernel_us": round(kernel_ms * 1e3, 3),
             "bytes_per_launch": bytes_per_launch,
         },
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps or (40 if case.lattice == "D2Q9" else 6))
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps or (40 if case.nz == 1 else 6))
     print(json.dumps(line), flush=True)
     s.close()
     return 0

@@ -50,7 +50,9 @@ typedef enum {
     LBM_MS_E_TAU_CLAMP = -9     /* a relaxation time hit tau_min / tau_max since the last check */
 } lbm_ms_status;
 
-enum { LBM_MS_D2Q9 = 0, LBM_MS_D3Q19 = 1, LBM_MS_D2Q5 = 2 };
+/* velocity sets, all with c_s^2 = 1/3 (Sec. 3.1): D2Q9; D3Q19; D2Q5 (rest 1/3, axis links 1/6);
+ * D3Q7 (rest 0, axis links 1/6) */
+enum { LBM_MS_D2Q9 = 0, LBM_MS_D3Q19 = 1, LBM_MS_D2Q5 = 2, LBM_MS_D3Q7 = 3 };
 
 /* population storage (collision arithmetic is FP64 for LBM_MS_FP64, FP32 otherwise; the
  * Maxwell-Stefan solve, residual, mass balance and overpotential are FP64 in every mode) */
@@ -74,8 +76,9 @@ enum { LBM_MS_INLET_DIRICHLET = 0, LBM_MS_INLET_WALL = 1 };
 enum { LBM_MS_BGK = 0, LBM_MS_TRT = 1 };
 
 typedef struct {
-    int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; not for batches) or LBM_MS_D3Q19 */
-    int nx, ny, nz;       /* nodes; nz must be 1 for D2Q9; nx >= 2 */
+    int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; D2Q5 not for batches), or
+                             LBM_MS_D3Q19, LBM_MS_D3Q7 (3D) */
+    int nx, ny, nz;       /* nodes; nz must be 1 for the 2D sets; nx >= 2 */
     double T;             /* K */
     double p;             /* Pa; C_t = p / (R T), R = 8.3145 */
     double D[9];          /* binary Maxwell-Stefan diffusivities D_ij [m^2/s], row-major 3x3,
@@ -94,7 +97,7 @@ typedef struct {
     double tau_min;       /* relaxation-time clamp; 0 selects 0.5 + 1e-9 */
     double tau_max;       /* 0 selects 1e6 */
     int tile_y;           /* launch shape (0 = default); see lbm_ms_tile_options */
-    int chunk_z;          /* D3Q19 planes per workgroup (0 = default) */
+    int chunk_z;          /* 3D: planes per workgroup (0 = default) */
     void* stream;         /* hipStream_t */
     int collision;        /* LBM_MS_BGK (0, the paper's) or LBM_MS_TRT */
     double trt_lambda;    /* TRT Lambda = (tau_even - 1/2)(tau - 1/2); <= 0 selects 1/4 */
@@ -131,8 +134,8 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
  * Size limit: the kernels address each population buffer (2 species x Q links x P elements of
  * the storage type, P = fluid nodes rounded up to 64, plus 192) with 32-bit byte offsets, so
  * E_ARG when it would exceed 4 GiB: about 28.2 M fluid nodes for D3Q19 FP32, 14.1 M for FP64,
- * 56.5 M for 16-bit storage (D2Q9: 59.6 M, 29.8 M, 119 M); with the NODE shift also at most
- * 268 M fluid nodes.  lbm_ms_workspace_bytes rejects boxes of more than 2^30 voxels. */
+ * 56.5 M for 16-bit storage (D2Q9: 59.6 M, 29.8 M, 119 M; D3Q7: 76.7 M, 38.3 M, 153 M); with
+ * the NODE shift also at most 268 M fluid nodes.  lbm_ms_workspace_bytes rejects boxes of more than 2^30 voxels. */
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
 
 /* The same clean-up on the host only (no device, no handle): solid_out = cleaned mask,

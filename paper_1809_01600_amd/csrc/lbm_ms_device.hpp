@@ -86,7 +86,25 @@ struct D3Q19 {
                                      W2F, W2F, W2F, W2F, W2F, W2F, W2F, W2F, W2F};
 };
 
-// sum of the weights of the links with e_x = +1 (1/6 for both sets)
+// D3Q7: rest and the six axis links.  c_s^2 = 1/3 (Sec. 3.1) makes the axis weight 1/6 and the
+// rest weight 0.
+struct D3Q7 {
+    static constexpr int Q = 7;
+    static constexpr int DIMS = 3;
+    static constexpr int ex[7] = {0, 1, -1, 0, 0, 0, 0};
+    static constexpr int ey[7] = {0, 0, 0, 1, -1, 0, 0};
+    static constexpr int ez[7] = {0, 0, 0, 0, 0, 1, -1};
+    static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
+    static constexpr double w[7] = {0.0, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    // FP32 weights with an exact unit sum and all six axis weights equal: 1/6 rounded down to a
+    // multiple of 2^-25, and the remainder 1 - 6 w1 = 2^-24 on the rest link
+    static constexpr long long M1 = (1LL << 25) / 6;
+    static constexpr float W1F = (float)((double)M1 / (double)(1LL << 25));
+    static constexpr float W0F = (float)((double)((1LL << 25) - 6 * M1) / (double)(1LL << 25));
+    static constexpr float wf[7] = {W0F, W1F, W1F, W1F, W1F, W1F, W1F};
+};
+
+// sum of the weights of the links with e_x = +1 (1/6 for every set)
 constexpr double W_OUT = 1.0 / 6.0;
 
 // Sum of a float weight table in FP64 (exact: every entry is a multiple of 2^-29 below one) and
@@ -98,8 +116,12 @@ constexpr double wf_sum()
     for (int k = 0; k < L::Q; ++k) t += (double)L::wf[k];
     return t;
 }
-static_assert(wf_sum<D2Q9>() == 1.0 && wf_sum<D3Q19>() == 1.0 && wf_sum<D2Q5>() == 1.0,
+static_assert(wf_sum<D2Q9>() == 1.0 && wf_sum<D3Q19>() == 1.0 && wf_sum<D2Q5>() == 1.0 &&
+                  wf_sum<D3Q7>() == 1.0,
               "float weights must sum to one");
+static_assert((double)D3Q7::W1F * (1LL << 25) == (double)D3Q7::M1 &&
+                  (double)D3Q7::W0F * (1LL << 25) == (double)((1LL << 25) - 6 * D3Q7::M1),
+              "D3Q7 weights are not floats");
 static_assert((double)D2Q5::W0F == 1.0 - 4.0 * (double)D2Q5::W1F, "D2Q5 rest weight is not a float");
 static_assert((double)D2Q9::W0F * (1LL << 25) == (double)((1LL << 25) - D2Q9::M1 - D2Q9::M2),
               "D2Q9 rest weight is not a float");

@@ -268,28 +268,26 @@ __device__ inline void stage_plane_refs3d(const StepArgs& a, int x0, int y0, int
 
 // Pull of one node of a 3D tile: NODE-shift references from the staged ring, else the plain
 // gather.  (cx, cy): the node's position in the staged plane, zr its relative plane.
-template <int P, bool NS, int RX, int RY, int NPL>
-__device__ inline void gather3d(const StepArgs& a, int i, const int (&si)[D3Q19::Q], bool inlet,
-                                bool outlet, typename Codec<P>::CT (&f)[2][D3Q19::Q], double& X0,
+template <class L, int P, bool NS, int RX, int RY, int NPL>
+__device__ inline void gather3d(const StepArgs& a, int i, const int (&si)[L::Q], bool inlet,
+                                bool outlet, typename Codec<P>::CT (&f)[2][L::Q], double& X0,
                                 double& X1, const double* sc, int zr, int cx, int cy)
 {
     if constexpr (NS)
-        gather_ns<D3Q19, P>(a, i, si, inlet, outlet, f, X0, X1,
-                            RefLds3<RX, RY, NPL>{sc, zr, cy * RX + cx});
+        gather_ns<L, P>(a, i, si, inlet, outlet, f, X0, X1, RefLds3<RX, RY, NPL>{sc, zr, cy * RX + cx});
     else
-        gather<D3Q19, P, false>(a, i, si, inlet, outlet, f, X0, X1);
+        gather<L, P, false>(a, i, si, inlet, outlet, f, X0, X1);
 }
 
 // ---------------------------------------------------------------------------------------------
-// 3D (D3Q19): one workgroup = 64 x TY column tile marching through CZ planes.  The index map is
+// 3D (D3Q19, D3Q7): one workgroup = 64 x TY column tile marching through CZ planes.  The index map is
 // staged in a 5-plane LDS ring one plane ahead; x/y gradients come from a 3-slot LDS ring of
 // plane moments (tile + halo ring), z gradients from the column's own rolling registers.  One
 // barrier per plane.
 // ---------------------------------------------------------------------------------------------
-template <int P, bool NS, int TY, int CZ>
+template <class L, int P, bool NS, int TY, int CZ>
 __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
 {
-    using L = D3Q19;
     using CT = typename Codec<P>::CT;
     constexpr int TX = 64, RX = TX + 4, RY = TY + 4, NPL = 5;
     constexpr int NHALO = 2 * TX + 2 * TY;
@@ -336,12 +334,12 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
         int si[L::Q];
         lds_sources<L, RX, RY, NPL>(sI, -1, lx + 2, ly + 2, x, a.nx, in_x ? im : -1, si);
         CT tf[2][L::Q];
-        gather3d<P, NS, RX, RY, NPL>(a, (in_x && im >= 0) ? im : 0, si, x == 0, x == a.nx - 1, tf, Xm0, Xm1,
+        gather3d<L, P, NS, RX, RY, NPL>(a, (in_x && im >= 0) ? im : 0, si, x == 0, x == a.nx - 1, tf, Xm0, Xm1,
                                      sC, -1, lx + 2, ly + 2);
         if (!(in_x && im >= 0)) Xm0 = Xm1 = 0.0;
         ic = in_x ? sI[((2) * RY + ly + 2) * RX + lx + 2] : -1;
         nbc = lds_sources<L, RX, RY, NPL>(sI, 0, lx + 2, ly + 2, x, a.nx, ic, si);
-        gather3d<P, NS, RX, RY, NPL>(a, ic < 0 ? 0 : ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1, sC, 0,
+        gather3d<L, P, NS, RX, RY, NPL>(a, ic < 0 ? 0 : ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1, sC, 0,
                                      lx + 2, ly + 2);
         if (ic < 0) Xc0 = Xc1 = 0.0;
         double h0 = 0.0, h1 = 0.0;
@@ -350,7 +348,7 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
             int hsi[L::Q];
             lds_sources<L, RX, RY, NPL>(sI, 0, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
             CT hf[2][L::Q];
-            gather3d<P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1,
+            gather3d<L, P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1,
                                          hf, h0, h1, sC, 0, hx + 2, hy + 2);
             if (hi < 0) h0 = h1 = 0.0;
         }
@@ -406,13 +404,13 @@ __global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
                 gather_finish<L, P>(a, rh, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
             }
         } else {
-            gather3d<P, NS, RX, RY, NPL>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1, sC,
+            gather3d<L, P, NS, RX, RY, NPL>(a, in_ < 0 ? 0 : in_, si, x == 0, x == a.nx - 1, fn, Xp0, Xp1, sC,
                                          zr, lx + 2, ly + 2);
             if (hwave) {
                 int hsi[L::Q];
                 lds_sources<L, RX, RY, NPL>(sI, zr, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
                 CT hf[2][L::Q];
-                gather3d<P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0,
+                gather3d<L, P, NS, RX, RY, NPL>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0,
                                              hjob && hgx == a.nx - 1, hf, h0, h1, sC, zr, hx + 2, hy + 2);
             }
         }
@@ -812,17 +810,24 @@ struct Ops {
     }
 };
 
+template <class L, int P, bool NS>
+static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int cz, int nblocks)
+{
+    if (ty == 4 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 4, 16>), dim3(nblocks), dim3(256), 0, st, a);
+    else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
+    else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
+    else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int P, bool NS>
 static hipError_t launch_step_p(hipStream_t st, const StepArgs& a, int lattice, int ty, int cz,
                                 int nblocks)
 {
-    if (lattice != 1) return hipErrorInvalidValue;
-    if (ty == 4 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 4, 16>), dim3(nblocks), dim3(256), 0, st, a);
-    else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
-    else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
-    else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (lattice == 1) return launch_step_l<D3Q19, P, NS>(st, a, ty, cz, nblocks);
+    if (lattice == 3) return launch_step_l<D3Q7, P, NS>(st, a, ty, cz, nblocks);
+    return hipErrorInvalidValue;
 }
 
 template <class L, int P, bool NS>
@@ -867,7 +872,7 @@ int tile_options(int lattice, int* ty, int* cz, int cap)
 {
     static const int t2[3] = {4, 8, 16};
     static const int t3[4][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}};
-    const bool d2 = lattice != 1;  // D2Q9 and D2Q5 share the 2D launch shapes
+    const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
     const int total = d2 ? 3 : 4;
     for (int i = 0; i < total && i < cap; ++i) {
         if (ty) ty[i] = d2 ? t2[i] : t3[i][0];
@@ -903,6 +908,7 @@ static hipError_t dispatch(int lattice, int prec, int ns, Args&&... args)
     }
     if (lattice == 0) { LBMMS_CASES(D2Q9) }
     else if (lattice == 2) { LBMMS_CASES(D2Q5) }
+    else if (lattice == 3) { LBMMS_CASES(D3Q7) }
     else { LBMMS_CASES(D3Q19) }
 #undef LBMMS_CASES
     return hipErrorInvalidValue;

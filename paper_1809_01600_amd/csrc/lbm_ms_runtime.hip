@@ -30,12 +30,16 @@ struct Layout {
     size_t tile_cap, ent_cap;
 };
 
-int q_of(int lattice) { return lattice == LBM_MS_D2Q9 ? 9 : (lattice == LBM_MS_D2Q5 ? 5 : 19); }
+int q_of(int lattice)
+{
+    return lattice == LBM_MS_D2Q9 ? 9 : lattice == LBM_MS_D2Q5 ? 5 : lattice == LBM_MS_D3Q7 ? 7 : 19;
+}
 bool known_lattice(int lattice)
 {
-    return lattice == LBM_MS_D2Q9 || lattice == LBM_MS_D3Q19 || lattice == LBM_MS_D2Q5;
+    return lattice == LBM_MS_D2Q9 || lattice == LBM_MS_D3Q19 || lattice == LBM_MS_D2Q5 ||
+           lattice == LBM_MS_D3Q7;
 }
-bool is_2d(int lattice) { return lattice != LBM_MS_D3Q19; }
+bool is_2d(int lattice) { return lattice == LBM_MS_D2Q9 || lattice == LBM_MS_D2Q5; }
 
 size_t elem_bytes(int prec)
 {
@@ -196,7 +200,7 @@ struct lbm_ms_s {
         a.nz = p.nz;
         a.tiles_x = (p.nx + 63) / 64;
         a.tiles_y = (p.ny + ty - 1) / ty;
-        a.chunks_z = (p.lattice == LBM_MS_D3Q19) ? (p.nz + cz - 1) / cz : 1;
+        a.chunks_z = !is_2d(p.lattice) ? (p.nz + cz - 1) / cz : 1;
         a.iD12 = 1.0 / Dl[1];
         a.iD13 = 1.0 / Dl[2];
         a.iD23 = 1.0 / Dl[5];
@@ -226,7 +230,7 @@ struct lbm_ms_s {
     int nblocks_step() const
     {
         const long long tx = (p.nx + 63) / 64, tyy = (p.ny + ty - 1) / ty;
-        const long long tz = (p.lattice == LBM_MS_D3Q19) ? (p.nz + cz - 1) / cz : 1;
+        const long long tz = !is_2d(p.lattice) ? (p.nz + cz - 1) / cz : 1;
         return (int)(tx * tyy * tz);
     }
     int sync() { return hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
@@ -287,6 +291,10 @@ HostLattice host_lattice(int lattice)
             H.e[k][0] = D2Q5::ex[k];
             H.e[k][1] = D2Q5::ey[k];
             H.e[k][2] = 0;
+        } else if (lattice == LBM_MS_D3Q7) {
+            H.e[k][0] = D3Q7::ex[k];
+            H.e[k][1] = D3Q7::ey[k];
+            H.e[k][2] = D3Q7::ez[k];
         } else {
             H.e[k][0] = D3Q19::ex[k];
             H.e[k][1] = D3Q19::ey[k];
@@ -420,9 +428,10 @@ int default_tile_y(const lbm_ms_params& p)
 {
     if (p.tile_y > 0) return p.tile_y;
     if (is_2d(p.lattice)) return p.ny >= 8 ? 8 : 4;
-    // measured on a 256^3 porous block: FP64 runs best with the 256-lane tiles (its 512-lane
-    // build spills), every other storage mode with the 512-lane ones
-    return p.precision == LBM_MS_FP64 ? 4 : 8;
+    // measured on a 256^3 porous block: D3Q19 FP64 runs best with the 256-lane tiles (its
+    // 512-lane build spills), every other storage mode with the 512-lane ones; D3Q7 builds
+    // without spills everywhere
+    return (p.precision == LBM_MS_FP64 && p.lattice == LBM_MS_D3Q19) ? 4 : 8;
 }
 
 int default_chunk_z(const lbm_ms_params& p)
@@ -580,6 +589,7 @@ int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w)
     };
     if (lattice == LBM_MS_D2Q9) put(D2Q9{});
     else if (lattice == LBM_MS_D2Q5) put(D2Q5{});
+    else if (lattice == LBM_MS_D3Q7) put(D3Q7{});
     else put(D3Q19{});
     return LBM_MS_OK;
 }

@@ -16,11 +16,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_ms.so")
 
-D2Q9, D3Q19, D2Q5 = 0, 1, 2
+D2Q9, D3Q19, D2Q5, D3Q7 = 0, 1, 2, 3
 BGK, TRT = 0, 1
 COLLISIONS = {"bgk": BGK, "trt": TRT}
-LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D2Q5": D2Q5}
-Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5}
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D2Q5": D2Q5, "D3Q7": D3Q7}
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5, "D3Q7": 7}
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 SHIFT_GLOBAL, SHIFT_NODE = 0, 1
 LOCAL_FLUX, STOICH = 0, 1

@@ -39,7 +39,8 @@ def test_cnn_symbols_exported_and_bound():
 
 
 def test_lattice_tables_match_the_oracle_as_sets():
-    for lat, name in ((lbm_ms.D2Q9, "D2Q9"), (lbm_ms.D3Q19, "D3Q19"), (lbm_ms.D2Q5, "D2Q5")):
+    for lat, name in ((lbm_ms.D2Q9, "D2Q9"), (lbm_ms.D3Q19, "D3Q19"), (lbm_ms.D2Q5, "D2Q5"),
+                      (lbm_ms.D3Q7, "D3Q7")):
         e, w = lbm_ms.lattice_info(lat)
         eo, wo = oracle.velocities(name)
         a = sorted((tuple(v), round(x, 15)) for v, x in zip(e.tolist(), w))
@@ -78,6 +79,7 @@ def test_workspace_bytes_and_validation():
 def test_tile_options_and_status_strings():
     assert (16, 0) in lbm_ms.tile_options(lbm_ms.D2Q9)
     assert all(cz > 0 for _, cz in lbm_ms.tile_options(lbm_ms.D3Q19))
+    assert lbm_ms.tile_options(lbm_ms.D3Q7) == lbm_ms.tile_options(lbm_ms.D3Q19)
     for code in range(-9, 1):
         assert lbm_ms.lib().lbm_ms_status_string(code).decode() != "unknown status"
 
@@ -93,7 +95,8 @@ def test_missing_library_fails_loudly(monkeypatch):
                                                  ("D2Q9", (1, 64, 64), 0.45, 2),
                                                  ("D3Q19", (9, 11, 13), 0.7, 3),
                                                  ("D2Q5", (1, 40, 30), 0.35, 4),
-                                                 ("D2Q5", (1, 64, 64), 0.3, 5)])
+                                                 ("D2Q5", (1, 64, 64), 0.3, 5),
+                                                 ("D3Q7", (9, 11, 13), 0.6, 6)])
 def test_host_clean_up_matches_oracle_labelling(lat, shape, frac, seed):
     rng = np.random.default_rng(seed)
     solid = (rng.random(shape) < frac).astype(np.uint8)

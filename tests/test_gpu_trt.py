@@ -38,6 +38,8 @@ def _percolating(lat, shape, seed0, **kw):
     ("D2Q9", (1, 40, 96), "fp32", lbm_ms.SHIFT_GLOBAL, 2e-6, False),
     ("D2Q9", (1, 40, 96), "bf16", lbm_ms.SHIFT_NODE, 2e-3, False),
     ("D3Q19", (9, 11, 40), "fp32", lbm_ms.SHIFT_NODE, 2e-6, True),
+    ("D3Q7", (9, 11, 40), "fp64", lbm_ms.SHIFT_GLOBAL, 1e-12, True),
+    ("D3Q7", (9, 11, 40), "fp32", lbm_ms.SHIFT_GLOBAL, 2e-6, False),
 ])
 def test_trt_short_run_matches_oracle(lat, shape, precision, shift, tol, source):
     case = _percolating(lat, shape, 500, j_A_cm2=0.5, tau_ref=5.0)

@@ -10,27 +10,29 @@ import oracle_windows as ow
 from paper_1809_01600_amd import inputs
 
 
-def _percolating(seed0):
+def _percolating(seed0, lat="D3Q19"):
     seed = seed0
     while True:
-        c = inputs.random_small(40, 12, 11, "D3Q19", seed=seed, solid_frac=0.2, tau_ref=3.0)
-        if oracle.label("D3Q19", c.mask())[1] > 0:
+        c = inputs.random_small(40, 12, 11, lat, seed=seed, solid_frac=0.2, tau_ref=3.0)
+        if oracle.label(lat, c.mask())[1] > 0:
             return c
         seed += 1
 
 
+@pytest.mark.parametrize("lat,mode", [("D3Q19", oracle.LOCAL_FLUX), ("D3Q7", oracle.LOCAL_FLUX),
+                                      ("D3Q7", oracle.STOICH)])
 @pytest.mark.parametrize("steps", [1, 2])
-def test_windows_reproduce_the_whole_oracle(steps):
-    case = _percolating(30)
+def test_windows_reproduce_the_whole_oracle(steps, lat, mode):
+    case = _percolating(30, lat)
     X0 = inputs.random_field(case.shape, seed=31, lo=0.2, hi=0.8)
-    whole = oracle.Oracle(case)
+    whole = oracle.Oracle(case, ms_mode=mode)
     whole.init_field(X0)
     whole.step(steps)
     Xw = whole.moments()
     mask, Q, eps = ow.full_inputs(case)
     assert np.array_equal(mask, whole.solid)
     columns = [(0, 0), (5, 3), (11, 10), (6, 7)]  # edges of the periodic block included
-    rows = ow.column_rows(case, X0, steps, columns, mask, Q, eps)
+    rows = ow.column_rows(case, X0, steps, columns, mask, Q, eps, ms_mode=mode)
     for (y, z), row in zip(columns, rows):
         assert np.array_equal(row, Xw[:, z, y, :]), (y, z, np.max(np.abs(row - Xw[:, z, y, :])))
 
