@@ -515,16 +515,34 @@ __device__ inline double rcp64(double d)
 // g0/g1: mole-fraction gradients of species 1, 2 per axis, except the x entry of an outlet node,
 // which is replaced here by Eq. 37's -[B] J (J = imposed lattice flux).  Returns 1/tau per
 // species; *hit is set when a clamp applied.
-template <int DIMS>
-__device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double (&g0)[3],
-                                double (&g1)[3], bool outlet, double& om0, double& om1, bool& hit)
+// The node's Maxwell-Stefan matrix [B] (Eq. 32) and, with RDET and the local flux-norm ratio,
+// the reciprocal of its determinant: everything of the solve that the gradients do not enter.
+struct MsMat {
+    double B00, B01, B10, B11, rdet;
+};
+
+template <bool RDET>
+__device__ inline MsMat ms_matrix(const StepArgs& a, double X0, double X1)
 {
     const double X2 = 1.0 - X0 - X1;
+    MsMat m;
     // Eq. 32: B_ii = X_i / D_in + sum_{k != i} X_k / D_ik,  B_ij = -X_i (1/D_ij - 1/D_in)
-    const double B00 = X0 * a.iD13 + X1 * a.iD12 + X2 * a.iD13;
-    const double B01 = -X0 * (a.iD12 - a.iD13);
-    const double B10 = -X1 * (a.iD12 - a.iD23);
-    const double B11 = X1 * a.iD23 + X0 * a.iD12 + X2 * a.iD23;
+    m.B00 = X0 * a.iD13 + X1 * a.iD12 + X2 * a.iD13;
+    m.B01 = -X0 * (a.iD12 - a.iD13);
+    m.B10 = -X1 * (a.iD12 - a.iD23);
+    m.B11 = X1 * a.iD23 + X0 * a.iD12 + X2 * a.iD23;
+    m.rdet = 0.0;
+    if (RDET && a.ms_mode == 0) m.rdet = rcp64(m.B00 * m.B11 - m.B01 * m.B10);
+    return m;
+}
+
+template <int DIMS, bool RDET>
+__device__ inline void ms_relax(const StepArgs& a, double X0, double X1, const MsMat& m,
+                                double (&g0)[3], double (&g1)[3], bool outlet, double& om0,
+                                double& om1, bool& hit)
+{
+    const double X2 = 1.0 - X0 - X1;
+    const double B00 = m.B00, B01 = m.B01, B10 = m.B10, B11 = m.B11;
     if (outlet) {
         g0[0] = -(B00 * a.Q0 + B01 * a.Q1);
         g1[0] = -(B10 * a.Q0 + B11 * a.Q1);
@@ -532,7 +550,7 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     double n0 = 0.0, n1 = 0.0;
     if (a.ms_mode == 0) {
         // Eq. 34 with Gamma = I: J = -[B]^-1 grad X (Cramer's rule), then |J| per species
-        const double rdet = rcp64(B00 * B11 - B01 * B10);
+        const double rdet = RDET ? m.rdet : rcp64(B00 * B11 - B01 * B10);
         double q0 = 0.0, q1 = 0.0;
 #pragma unroll
         for (int dd = 0; dd < DIMS; ++dd) {
@@ -567,6 +585,13 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double 
     hit = h;
     om0 = w0;
     om1 = w1;
+}
+
+template <int DIMS>
+__device__ inline void ms_relax(const StepArgs& a, double X0, double X1, double (&g0)[3],
+                                double (&g1)[3], bool outlet, double& om0, double& om1, bool& hit)
+{
+    ms_relax<DIMS, false>(a, X0, X1, ms_matrix<false>(a, X0, X1), g0, g1, outlet, om0, om1, hit);
 }
 
 // central difference, one-sided next to a missing or solid neighbour, zero between two
