@@ -74,7 +74,7 @@ static void build_lattice(int lattice, orc_lattice* L)
 {
     memset(L, 0, sizeof(*L));
     if (lattice == 2) {
-        /* D2Q5 (the paper names it beside D2Q9 in Sec. 3.1): rest and the four axis links, with
+        /* D2Q5 (the paper names it beside D2Q9 in Sec. 2.3): rest and the four axis links, with
          * weights 1/3 and 1/6, which give sum_a w_a e_a e_a = I / 3 like D2Q9 */
         static const int ex[5] = {0, 1, 0, -1, 0}, ey[5] = {0, 0, 1, 0, -1};
         L->q = 5;

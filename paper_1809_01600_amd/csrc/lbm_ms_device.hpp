@@ -44,7 +44,7 @@ struct D2Q9 {
     static constexpr float wf[9] = {W0F, W1F, W1F, W1F, W1F, W2F, W2F, W2F, W2F};
 };
 
-// D2Q5, named beside D2Q9 in Sec. 3.1: rest and the four axis links in Eq. 2's order, weights
+// D2Q5, named beside D2Q9 in Sec. 2.3: rest and the four axis links in Eq. 2's order, weights
 // 1/3 and 1/6, the same second moment c_s^2 = 1/3 with five populations instead of nine.
 struct D2Q5 {
     static constexpr int Q = 5;

@@ -1,4 +1,4 @@
-"""The D2Q5 lattice (rest and axis links, weights 1/3 and 1/6; named beside D2Q9 in Sec. 3.1) on
+"""The D2Q5 lattice (rest and axis links, weights 1/3 and 1/6; named beside D2Q9 in Sec. 2.3) on
 the GPU through the C ABI, against the oracle's D2Q5 (pinned on the CPU: isotropy, exact
 variance, the discrete Stefan chain, conservation, 4-connected clean-up): porous slices on every
 2D tile height, the storage modes, the full 1024^2 slice, and the y-invariant steady state, which
