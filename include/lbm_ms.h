@@ -76,7 +76,7 @@ enum { LBM_MS_INLET_DIRICHLET = 0, LBM_MS_INLET_WALL = 1 };
 enum { LBM_MS_BGK = 0, LBM_MS_TRT = 1 };
 
 typedef struct {
-    int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; D2Q5 not for batches), or
+    int lattice;          /* LBM_MS_D2Q9, LBM_MS_D2Q5 (2D, nz = 1; also for batches), or
                              LBM_MS_D3Q19, LBM_MS_D3Q7 (3D) */
     int nx, ny, nz;       /* nodes; nz must be 1 for the 2D sets; nx >= 2 */
     double T;             /* K */
@@ -235,7 +235,7 @@ int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, i
 int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z);
 
 /* ---------------------------------------------------------------------------------------------
- * Batched solves (D2Q9): many independent porous slices of uneven size, each with its own
+ * Batched solves (D2Q9 or D2Q5): many independent porous slices of uneven size, each with its own
  * geometry, inlet composition and current density, advanced together.  Every step is one kernel
  * launch over the combined tile work list of all still-active instances; a converge call captures
  * check_every steps into a hipGraph on the batch's own stream and replays it, checks every

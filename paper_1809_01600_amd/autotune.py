@@ -43,6 +43,10 @@ def _store(data):
         pass  # a read-only home only loses the cache
 
 
+def _lattice_name(code):
+    return next(name for name, c in lbm_ms.LATTICES.items() if c == code)
+
+
 def _key(kind, lattice, precision, shift, dims):
     return "%s|%s|p%d|s%d|%s" % (kind, lattice, precision, shift, "x".join(str(d) for d in dims))
 
@@ -50,8 +54,7 @@ def _key(kind, lattice, precision, shift, dims):
 def tune(solver, steps: int = 100, warmup: int = 10, use_cache: bool = True):
     """Pick the fastest tile shape for a single-problem solver (state is restored after)."""
     p = solver.params
-    lat = "D2Q9" if p.lattice == lbm_ms.D2Q9 else "D3Q19"
-    key = _key("single", lat, p.precision, p.shift_mode, (p.nx, p.ny, p.nz))
+    key = _key("single", _lattice_name(p.lattice), p.precision, p.shift_mode, (p.nx, p.ny, p.nz))
     data = _load() if use_cache else {}
     if key in data:
         ty, cz = data[key]["tile"]
@@ -79,7 +82,7 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
     inlet composition and advances it; initialize again before a solve."""
     p = batch.params
     sizes = sorted((c.nx, c.ny) for c in batch.cases)
-    key = _key("batch", "D2Q9", p.precision, p.shift_mode,
+    key = _key("batch", _lattice_name(p.lattice), p.precision, p.shift_mode,
                (len(sizes), sum(a * b for a, b in sizes)))
     data = _load() if use_cache else {}
     if key in data:
@@ -87,7 +90,7 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
         return tuple(data[key]["tile"])
     timings = {}
     batch.init()
-    for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9, p.precision):
+    for ty, _ in lbm_ms.tile_options(p.lattice, p.precision):
         batch.set_tile(ty)
         batch.step(warmup)
         timings[ty] = batch.time_steps(steps) / steps

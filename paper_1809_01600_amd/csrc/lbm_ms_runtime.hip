@@ -1210,7 +1210,7 @@ struct lbm_ms_batch_s {
     {
         const StepArgs* tab = reinterpret_cast<const StepArgs*>(ws + off_tab) + (size_t)cur * count;
         return launch_step2d(stream, tab, reinterpret_cast<const int4*>(ws + off_tiles),
-                             reinterpret_cast<const unsigned*>(ws + off_ent), ntiles, LBM_MS_D2Q9,
+                             reinterpret_cast<const unsigned*>(ws + off_ent), ntiles, common.lattice,
                              common.precision, node_shift(common) ? 1 : 0, ty);
     }
     void advance(int64_t n)
@@ -1280,7 +1280,7 @@ bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
                   std::vector<size_t>* offs, size_t* off_tab, size_t* off_tiles, size_t* off_ent,
                   size_t* tile_cap, size_t* ent_cap, size_t* total)
 {
-    if (!common || !inst || count <= 0 || common->lattice != LBM_MS_D2Q9) return false;
+    if (!common || !inst || count <= 0 || !is_2d(common->lattice)) return false;
     size_t off = 0, tc = 0, ec = 0;
     auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
     if (offs) offs->clear();
@@ -1362,7 +1362,7 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     b->ent_cap = ec;
     b->count = count;
     b->ty = default_tile_y(*common);
-    if (b->ty > 16 || !tile_ok(LBM_MS_D2Q9, b->ty, 0)) b->ty = 8;
+    if (b->ty > 16 || !tile_ok(common->lattice, b->ty, 0)) b->ty = 8;
     int rc = LBM_MS_OK;
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -1427,7 +1427,7 @@ int lbm_ms_batch_stats(lbm_ms_batch_t b, int* active, int64_t* fluid, int* tiles
 int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y)
 {
     if (!b) return LBM_MS_E_ARG;
-    if (!tile_ok(LBM_MS_D2Q9, tile_y, 0)) return b->fail(LBM_MS_E_ARG, "launch shape not compiled");
+    if (!tile_ok(b->common.lattice, tile_y, 0)) return b->fail(LBM_MS_E_ARG, "launch shape not compiled");
     int rc = b->enter();
     if (rc) return rc;
     b->ty = tile_y;

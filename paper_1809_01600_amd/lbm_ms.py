@@ -429,7 +429,8 @@ class _InstanceView(Solver):
 
 
 class Batch:
-    """Many D2Q9 problems advanced by one launch per step (see lbm_ms_batch_* in lbm_ms.h)."""
+    """Many 2D (D2Q9 or D2Q5) problems advanced by one launch per step (see lbm_ms_batch_* in
+    lbm_ms.h)."""
 
     def __init__(self, cases, precision="fp32", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
                  tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0):
@@ -443,8 +444,8 @@ class Batch:
             for f in shared:
                 if getattr(c, f) != getattr(c0, f):
                     raise ValueError("batch members must share %s" % f)
-        if c0.lattice != "D2Q9" or any(c.nz != 1 for c in self.cases):
-            raise ValueError("batched solves are two-dimensional (D2Q9)")
+        if c0.lattice not in ("D2Q9", "D2Q5") or any(c.nz != 1 for c in self.cases):
+            raise ValueError("batched solves are two-dimensional (D2Q9 or D2Q5)")
         self.stream = torch.cuda.current_stream(torch.device(device))
         self.params = make_params(c0, precision, shift_mode, ms_mode, INLET_DIRICHLET, eps_flux,
                                   0.0, 0.0, tile_y, 0, self.stream.cuda_stream, collision, trt_lambda)

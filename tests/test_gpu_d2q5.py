@@ -1,8 +1,8 @@
 """The D2Q5 lattice (rest and axis links, weights 1/3 and 1/6; named beside D2Q9 in Sec. 2.3) on
 the GPU through the C ABI, against the oracle's D2Q5 (pinned on the CPU: isotropy, exact
 variance, the discrete Stefan chain, conservation, 4-connected clean-up): porous slices on every
-2D tile height, the storage modes, the full 1024^2 slice, and the y-invariant steady state, which
-D2Q5 and D2Q9 share exactly (the same D1Q3 x-marginal)."""
+2D tile height, the storage modes, the full 1024^2 slice, the y-invariant steady state, which
+D2Q5 and D2Q9 share exactly (the same D1Q3 x-marginal), and batches of ragged D2Q5 slices."""
 
 import numpy as np
 import pytest
@@ -124,3 +124,59 @@ def test_conserves_species_one_step():
     inv2, _, _ = s.mass_balance()
     assert np.allclose(inv2 - inv, inflow - outflow, rtol=0, atol=1e-13 * np.max(inv))
     s.close()
+
+
+def _batch_cases(seed0, sizes, js):
+    out = []
+    seed = seed0
+    for (nx, ny), j in zip(sizes, js):
+        while True:
+            c = inputs.porous_2d(n=nx, ny=ny, seed=seed, j_A_cm2=j, tau_ref=5.0, r_lo=3.0, r_hi=8.0)
+            c.lattice = "D2Q5"
+            seed += 1
+            if oracle.label("D2Q5", c.mask())[1] > 0:
+                break
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("precision,ty,mode", [("fp64", 4, lbm_ms.STOICH), ("fp32", 8, lbm_ms.LOCAL_FLUX),
+                                               ("bf16", 16, lbm_ms.LOCAL_FLUX)])
+def test_batch_equals_single_solves_and_oracle(precision, ty, mode):
+    """Ragged D2Q5 instances in one batch: bitwise equal to single D2Q5 solves with the same
+    tile height, and in FP64 equal to the oracle.  The FP64 comparison uses the stoichiometric
+    ratio: on the 129 x 64 instance the local flux-norm ratio of Eq. 24 is ill-conditioned, and
+    the oracle itself, started with 1e-16 noise, moves by 2.9e-10 in 120 steps (2.8e-16 with
+    the stoichiometric ratio)."""
+    cases = _batch_cases(600, ((70, 33), (129, 64), (200, 17)), (0.4, 1.2, 2.0))
+    b = lbm_ms.Batch(cases, precision=precision, tile_y=ty, ms_mode=mode)
+    b.init()
+    b.step(120)
+    for k, c in enumerate(cases):
+        s = lbm_ms.Solver(c, precision=precision, tile_y=ty, ms_mode=mode)
+        s.init()
+        s.step(120)
+        assert np.array_equal(b.instance(k).get_fields(), s.get_fields()), k
+        s.close()
+        if precision == "fp64":
+            o = oracle.Oracle(c, ms_mode=oracle.STOICH)
+            o.init_uniform()
+            o.step(120)
+            assert np.max(np.abs(b.instance(k).get_fields() - o.moments())) < 1e-12, k
+    b.close()
+
+
+def test_batch_converges_with_graphs():
+    cases = _batch_cases(620, ((48, 24), (64, 40)), (0.5, 1.5))
+    b = lbm_ms.Batch(cases, precision="fp64", ms_mode=lbm_ms.STOICH)
+    b.init()
+    b.converge(1e-10, 400_000, check_every=500, raise_on_fail=False)
+    assert all(int(v) == 0 for v in b.status), b.status
+    eta = b.overpotential()
+    for k, c in enumerate(cases):
+        s = lbm_ms.Solver(c, precision="fp64", ms_mode=lbm_ms.STOICH)
+        s.init()
+        s.converge(1e-10, 400_000, check_every=500)
+        assert abs(s.overpotential() - float(eta[k])) < 1e-9, k
+        s.close()
+    b.close()
