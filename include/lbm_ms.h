@@ -135,7 +135,8 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
  * the storage type, P = fluid nodes rounded up to 64, plus 192) with 32-bit byte offsets, so
  * E_ARG when it would exceed 4 GiB: about 28.2 M fluid nodes for D3Q19 FP32, 14.1 M for FP64,
  * 56.5 M for 16-bit storage (D2Q9: 59.6 M, 29.8 M, 119 M; D3Q7: 76.7 M, 38.3 M, 153 M); with
- * the NODE shift also at most 268 M fluid nodes.  lbm_ms_workspace_bytes rejects boxes of more than 2^30 voxels. */
+ * the NODE shift also at most 268 M fluid nodes.  lbm_ms_workspace_bytes rejects boxes of more
+ * than 2^30 voxels. */
 int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host);
 
 /* The same clean-up on the host only (no device, no handle): solid_out = cleaned mask,
