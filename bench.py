@@ -280,7 +280,7 @@ def run_batch(args):
             "ms_solve": "fp64",
             "check_every": args.check_every,
             "graphs": True,
-            "tile": [64, int(tile[0])],
+            "tile": [64, int(tile[0]), int(tile[1])],
             "active_at_end": int(active),
             "failed_checks": failed,
             "node_mlups": round(updates / elapsed / 1e6, 1),

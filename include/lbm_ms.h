@@ -97,7 +97,9 @@ typedef struct {
     double tau_min;       /* relaxation-time clamp; 0 selects 0.5 + 1e-9 */
     double tau_max;       /* 0 selects 1e6 */
     int tile_y;           /* launch shape (0 = default); see lbm_ms_tile_options */
-    int chunk_z;          /* 3D: planes per workgroup (0 = default) */
+    int chunk_z;          /* 3D: planes per workgroup (0 = default).  2D: the row limit of packed
+                             tiles (see lbm_ms_tile_options); 0 = default, which is 12 (packed)
+                             when tile_y is 8 and fixed 64 x tile_y tiles otherwise */
     void* stream;         /* hipStream_t */
     int collision;        /* LBM_MS_BGK (0, the paper's) or LBM_MS_TRT */
     double trt_lambda;    /* TRT Lambda = (tau_even - 1/2)(tau - 1/2); <= 0 selects 1/4 */
@@ -229,7 +231,10 @@ int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info);
 int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w);
 
 /* Launch shapes compiled for a lattice: writes up to cap (tile_y, chunk_z) pairs, returns the
- * count (chunk_z is 0 for D2Q9). */
+ * count.  3D: 64 x tile_y columns marching chunk_z planes.  2D: workgroups of 32 tile_y lanes,
+ * one fluid node per lane; chunk_z = 0 for fixed 64 x tile_y tiles (a denser tile is split into
+ * parts), chunk_z > 0 for packed tiles that grow row by row in each 64-wide strip up to chunk_z
+ * rows or 32 tile_y fluid nodes. */
 int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap);
 
 /* Change the launch shape of an existing handle (one of lbm_ms_tile_options). */
@@ -298,8 +303,9 @@ lbm_ms_t lbm_ms_batch_instance(lbm_ms_batch_t b, int k);
 /* Active instances, total fluid nodes of the active instances, and active tiles. */
 int lbm_ms_batch_stats(lbm_ms_batch_t b, int* active, int64_t* fluid_nodes, int* tiles);
 
-/* Launch shape of every instance (one of lbm_ms_tile_options for D2Q9). */
-int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y);
+/* Launch shape of every instance: one (tile_y, rows) pair of lbm_ms_tile_options for the batch's
+ * lattice (rows = 0: fixed 64 x tile_y tiles, else packed tiles of at most rows rows). */
+int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y, int rows);
 
 /* Use (1) or bypass (0) hipGraph capture in lbm_ms_batch_converge (default 1). */
 int lbm_ms_batch_use_graphs(lbm_ms_batch_t b, int enable);

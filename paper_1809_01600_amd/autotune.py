@@ -86,19 +86,19 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
                (len(sizes), sum(a * b for a, b in sizes)))
     data = _load() if use_cache else {}
     if key in data:
-        batch.set_tile(data[key]["tile"][0])
+        batch.set_tile(*data[key]["tile"])
         return tuple(data[key]["tile"])
     timings = {}
     batch.init()
-    for ty, _ in lbm_ms.tile_options(p.lattice, p.precision):
-        batch.set_tile(ty)
+    for ty, rows in lbm_ms.tile_options(p.lattice, p.precision):
+        batch.set_tile(ty, rows)
         batch.step(warmup)
-        timings[ty] = batch.time_steps(steps) / steps
+        timings[(ty, rows)] = batch.time_steps(steps) / steps
     best = min(timings, key=timings.get)
-    batch.set_tile(best)
+    batch.set_tile(*best)
     data = _load()
-    data[key] = {"tile": [best, 0], "ms_per_step": {str(k): v for k, v in timings.items()},
+    data[key] = {"tile": list(best), "ms_per_step": {"%d,%d" % k: v for k, v in timings.items()},
                  "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     if use_cache:
         _store(data)
-    return (best, 0)
+    return best

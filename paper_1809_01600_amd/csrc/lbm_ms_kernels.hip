@@ -142,15 +142,17 @@ __device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[L::Q],
 template <int P, bool NS>
 constexpr int step2d_min_blocks(int ty) { return (P != P_F64 && !NS) ? 64 / ty : 1; }
 
-template <class L, int P, bool NS, int TY>
+// TYR: rows of the staged region and moment tile.  TYR = TY for fixed 64 x TY tiles; a larger
+// TYR for packed tiles, which the host grows row by row up to TYR rows or 32 TY fluid nodes.
+template <class L, int P, bool NS, int TY, int TYR>
 __global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_step2d(const StepArgs* __restrict__ insts,
                                                     const int4* __restrict__ tiles,
                                                     const unsigned* __restrict__ ent)
 {
     using CT = typename Codec<P>::CT;
-    constexpr int TX = 64, RX = TX + 4, RY = TY + 4, BS = 32 * TY;
+    constexpr int TX = 64, RX = TX + 4, RY = TYR + 4, BS = 32 * TY;
     __shared__ int sI[RY * RX];
-    __shared__ double sX[2][TY + 2][TX + 2];
+    __shared__ double sX[2][TYR + 2][TX + 2];
     __shared__ double sC[NS ? 2 * RY * RX : 1];  // NODE shift: staged references
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -858,51 +860,59 @@ static hipError_t launch_step_p(hipStream_t st, const StepArgs& a, int lattice, 
 
 template <class L, int P, bool NS>
 static hipError_t launch_step2d_p(hipStream_t st, const StepArgs* insts, const int4* tiles,
-                                  const unsigned* ent, int ntiles, int ty)
+                                  const unsigned* ent, int ntiles, int ty, int rows)
 {
     if (ntiles <= 0) return hipSuccess;
-    switch (ty) {
-    case 4: hipLaunchKernelGGL((k_step2d<L, P, NS, 4>), dim3(ntiles), dim3(32 * 4), 0, st, insts, tiles, ent); break;
-    case 8: hipLaunchKernelGGL((k_step2d<L, P, NS, 8>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent); break;
-    case 16: hipLaunchKernelGGL((k_step2d<L, P, NS, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent); break;
-    default: return hipErrorInvalidValue;
-    }
+    if (ty == 4 && rows == 0)
+        hipLaunchKernelGGL((k_step2d<L, P, NS, 4, 4>), dim3(ntiles), dim3(32 * 4), 0, st, insts, tiles, ent);
+    else if (ty == 8 && rows == 0)
+        hipLaunchKernelGGL((k_step2d<L, P, NS, 8, 8>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent);
+    else if (ty == 16 && rows == 0)
+        hipLaunchKernelGGL((k_step2d<L, P, NS, 16, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent);
+    else if (ty == 8 && rows == 12)
+        hipLaunchKernelGGL((k_step2d<L, P, NS, 8, 12>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 template <class L>
 static hipError_t launch_step2d_l(hipStream_t st, const StepArgs* insts, const int4* tiles,
-                                  const unsigned* ent, int ntiles, int prec, int node_shift, int ty)
+                                  const unsigned* ent, int ntiles, int prec, int node_shift, int ty,
+                                  int rows)
 {
     switch (prec) {
-    case P_F64: return launch_step2d_p<L, P_F64, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_F32: return node_shift ? launch_step2d_p<L, P_F32, true>(st, insts, tiles, ent, ntiles, ty)
-                                  : launch_step2d_p<L, P_F32, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_F16: return node_shift ? launch_step2d_p<L, P_F16, true>(st, insts, tiles, ent, ntiles, ty)
-                                  : launch_step2d_p<L, P_F16, false>(st, insts, tiles, ent, ntiles, ty);
-    case P_BF16: return node_shift ? launch_step2d_p<L, P_BF16, true>(st, insts, tiles, ent, ntiles, ty)
-                                   : launch_step2d_p<L, P_BF16, false>(st, insts, tiles, ent, ntiles, ty);
+    case P_F64: return launch_step2d_p<L, P_F64, false>(st, insts, tiles, ent, ntiles, ty, rows);
+    case P_F32: return node_shift ? launch_step2d_p<L, P_F32, true>(st, insts, tiles, ent, ntiles, ty, rows)
+                                  : launch_step2d_p<L, P_F32, false>(st, insts, tiles, ent, ntiles, ty, rows);
+    case P_F16: return node_shift ? launch_step2d_p<L, P_F16, true>(st, insts, tiles, ent, ntiles, ty, rows)
+                                  : launch_step2d_p<L, P_F16, false>(st, insts, tiles, ent, ntiles, ty, rows);
+    case P_BF16: return node_shift ? launch_step2d_p<L, P_BF16, true>(st, insts, tiles, ent, ntiles, ty, rows)
+                                   : launch_step2d_p<L, P_BF16, false>(st, insts, tiles, ent, ntiles, ty, rows);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,
-                         const unsigned* ent, int ntiles, int lattice, int prec, int node_shift, int ty)
+                         const unsigned* ent, int ntiles, int lattice, int prec, int node_shift, int ty,
+                         int rows)
 {
-    if (lattice == 2) return launch_step2d_l<D2Q5>(st, insts, tiles, ent, ntiles, prec, node_shift, ty);
-    if (lattice == 0) return launch_step2d_l<D2Q9>(st, insts, tiles, ent, ntiles, prec, node_shift, ty);
+    if (lattice == 2) return launch_step2d_l<D2Q5>(st, insts, tiles, ent, ntiles, prec, node_shift, ty, rows);
+    if (lattice == 0) return launch_step2d_l<D2Q9>(st, insts, tiles, ent, ntiles, prec, node_shift, ty, rows);
     return hipErrorInvalidValue;
 }
 
 int tile_options(int lattice, int* ty, int* cz, int cap)
 {
-    static const int t2[3] = {4, 8, 16};
+    // 2D: (lanes / 32, 0) for fixed 64 x TY tiles, (lanes / 32, rows) for packed tiles of at
+    // most `rows` rows; 3D: (TY, planes per workgroup)
+    static const int t2[4][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 12}};
     static const int t3[4][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}};
     const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
-    const int total = d2 ? 3 : 4;
+    const int total = 4;
     for (int i = 0; i < total && i < cap; ++i) {
-        if (ty) ty[i] = d2 ? t2[i] : t3[i][0];
-        if (cz) cz[i] = d2 ? 0 : t3[i][1];
+        if (ty) ty[i] = d2 ? t2[i][0] : t3[i][0];
+        if (cz) cz[i] = d2 ? t2[i][1] : t3[i][1];
     }
     return total;
 }

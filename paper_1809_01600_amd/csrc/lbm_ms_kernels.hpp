@@ -10,9 +10,11 @@ namespace lbmms {
 int tile_options(int lattice, int* ty, int* cz, int cap);
 hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,
                        int ty, int cz, int nblocks);
-// 2D work-list step: insts = instance table of this step's parity, tiles = 2 int4 per tile
+// 2D work-list step: insts = instance table of this step's parity, tiles = 2 int4 per tile;
+// 32 ty lanes per workgroup, rows = 0 for fixed 64 x ty tiles, else the packed tiles' row limit
 hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,
-                         const unsigned* ent, int ntiles, int lattice, int prec, int node_shift, int ty);
+                         const unsigned* ent, int ntiles, int lattice, int prec, int node_shift, int ty,
+                         int rows);
 hipError_t launch_init(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
                        const double* X, double u0, double u1);
 hipError_t launch_residual(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,

@@ -148,7 +148,7 @@ _SIGNATURES = [
     ("lbm_ms_batch_stats", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int)]),
-    ("lbm_ms_batch_set_tile", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("lbm_ms_batch_set_tile", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
     ("lbm_ms_batch_use_graphs", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lbm_ms_batch_last_error", ctypes.c_char_p, [_VP]),
     ("lbm_ms_batch_destroy", None, [_VP]),
@@ -433,7 +433,7 @@ class Batch:
     lbm_ms.h)."""
 
     def __init__(self, cases, precision="fp32", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
-                 tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0):
+                 tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0, rows=0):
         import torch
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -448,7 +448,7 @@ class Batch:
             raise ValueError("batched solves are two-dimensional (D2Q9 or D2Q5)")
         self.stream = torch.cuda.current_stream(torch.device(device))
         self.params = make_params(c0, precision, shift_mode, ms_mode, INLET_DIRICHLET, eps_flux,
-                                  0.0, 0.0, tile_y, 0, self.stream.cuda_stream, collision, trt_lambda)
+                                  0.0, 0.0, tile_y, rows, self.stream.cuda_stream, collision, trt_lambda)
         n = len(self.cases)
         self._masks = [np.ascontiguousarray(c.mask(), dtype=np.uint8).reshape(-1) for c in self.cases]
         self.desc = (lbm_ms_instance_desc * n)()
@@ -539,8 +539,8 @@ class Batch:
         self._check(lib().lbm_ms_batch_stats(self.b, ctypes.byref(a), ctypes.byref(nf), ctypes.byref(t)))
         return a.value, nf.value, t.value
 
-    def set_tile(self, tile_y):
-        self._check(lib().lbm_ms_batch_set_tile(self.b, int(tile_y)))
+    def set_tile(self, tile_y, rows=0):
+        self._check(lib().lbm_ms_batch_set_tile(self.b, int(tile_y), int(rows)))
 
     def use_graphs(self, enable=True):
         self._check(lib().lbm_ms_batch_use_graphs(self.b, 1 if enable else 0))

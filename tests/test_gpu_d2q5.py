@@ -36,10 +36,10 @@ def _perm():
     return [eo.tolist().index(v) for v in e.tolist()]
 
 
-@pytest.mark.parametrize("ty", [4, 8, 16])
-def test_porous_slice_matches_oracle_on_every_tile(ty):
+@pytest.mark.parametrize("ty,rows", [(4, 0), (8, 0), (16, 0), (8, 12)])
+def test_porous_slice_matches_oracle_on_every_tile(ty, rows):
     case = _percolating(96, 40, 200, tau_ref=3.0)
-    s = lbm_ms.Solver(case, precision="fp64", tile_y=ty)
+    s = lbm_ms.Solver(case, precision="fp64", tile_y=ty, chunk_z=rows)
     o = oracle.Oracle(case)
     assert np.array_equal(s.get_geometry(), o.solid)
     s.init()
@@ -49,7 +49,7 @@ def test_porous_slice_matches_oracle_on_every_tile(ty):
     err = float(np.max(np.abs(s.get_fields() - o.moments())))
     fo, _, _, _ = o.collide()
     errf = float(np.max(np.abs(s.get_populations() - fo[:, _perm()])))
-    print("D2Q5 tile %d: max |dX| %.3e, max |df*| %.3e" % (ty, err, errf))
+    print("D2Q5 tile (%d, %d): max |dX| %.3e, max |df*| %.3e" % (ty, rows, err, errf))
     assert err <= 1e-12 and errf <= 1e-12
     s.close()
 

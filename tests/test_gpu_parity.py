@@ -88,8 +88,8 @@ def test_stefan_tube_fp64_5000_steps(mode):
 def test_porous_2d_fp64_every_tile_shape(mode):
     case = _percolating_2d(150, 70, seed0=3, tau_ref=5.0)  # ragged in x (150 = 2*64 + 22) and y
     o = None
-    for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9):
-        s, o2 = _pair(case, ms_mode=mode, tile_y=ty)
+    for ty, rows in lbm_ms.tile_options(lbm_ms.D2Q9):
+        s, o2 = _pair(case, ms_mode=mode, tile_y=ty, chunk_z=rows)
         if o is None:
             o = o2
             _check_setup(s, o)
