@@ -483,10 +483,15 @@ int default_tile_y(const lbm_ms_params& p)
 
 int default_chunk_z(const lbm_ms_params& p)
 {
-    // 2D: the packed tiles' row limit.  Packed 64-wide tiles of up to 12 rows and 256 fluid nodes
-    // measured faster than fixed 64 x 8 tiles on every 2D workload (64-slice batch 5%, D2Q5 slice
-    // 7-11%, D2Q9 slice 0-4%): their lanes stay nearly full and no tile splits.
-    if (is_2d(p.lattice)) return p.chunk_z > 0 ? p.chunk_z : (default_tile_y(p) == 8 ? 12 : 0);
+    // 2D: the packed tiles' row limit.  Packed 64-wide tiles of up to 256 fluid nodes measured
+    // faster than fixed 64 x 8 tiles on every 2D workload: their lanes stay nearly full and no
+    // tile splits.  Best row limit on the 1024^2 slice: 9 for D2Q9 (17.3 us; 12 rows 17.9, fixed
+    // 18.5), 12 for D2Q5 (12.5 us; 10 rows 13.0, fixed 14.0).
+    if (is_2d(p.lattice)) {
+        if (p.chunk_z > 0) return p.chunk_z;
+        if (default_tile_y(p) != 8) return 0;
+        return p.lattice == LBM_MS_D2Q5 ? 12 : 9;
+    }
     if (p.chunk_z > 0) return p.chunk_z;
     return p.nz >= 128 ? 32 : 16;
 }

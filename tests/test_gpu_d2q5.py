@@ -36,7 +36,7 @@ def _perm():
     return [eo.tolist().index(v) for v in e.tolist()]
 
 
-@pytest.mark.parametrize("ty,rows", [(4, 0), (8, 0), (16, 0), (8, 12)])
+@pytest.mark.parametrize("ty,rows", [(4, 0), (8, 0), (16, 0), (8, 9), (8, 12)])
 def test_porous_slice_matches_oracle_on_every_tile(ty, rows):
     case = _percolating(96, 40, 200, tau_ref=3.0)
     s = lbm_ms.Solver(case, precision="fp64", tile_y=ty, chunk_z=rows)
