@@ -485,12 +485,14 @@ int default_chunk_z(const lbm_ms_params& p)
 {
     // 2D: the packed tiles' row limit.  Packed 64-wide tiles of up to 256 fluid nodes measured
     // faster than fixed 64 x 8 tiles on every 2D workload: their lanes stay nearly full and no
-    // tile splits.  Best row limit on the 1024^2 slice: 9 for D2Q9 (17.3 us; 12 rows 17.9, fixed
-    // 18.5), 12 for D2Q5 (12.5 us; 10 rows 13.0, fixed 14.0).
+    // tile splits.  Best row limit on the 1024^2 slice: 9 for D2Q9 in every storage mode (FP32
+    // 17.3 us; 12 rows 17.9, fixed 18.5), 12 for D2Q5 with global-shift or FP64 storage (FP32
+    // 12.5 us; 10 rows 13.0, fixed 14.0) and 9 for D2Q5 with the NODE shift, whose staged
+    // references make 12-row tiles slower than fixed ones (FP32 18.0 us; 12 rows 19.4, fixed 18.3).
     if (is_2d(p.lattice)) {
         if (p.chunk_z > 0) return p.chunk_z;
         if (default_tile_y(p) != 8) return 0;
-        return p.lattice == LBM_MS_D2Q5 ? 12 : 9;
+        return (p.lattice == LBM_MS_D2Q5 && !node_shift(p)) ? 12 : 9;
     }
     if (p.chunk_z > 0) return p.chunk_z;
     return p.nz >= 128 ? 32 : 16;
