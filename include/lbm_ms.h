@@ -230,6 +230,17 @@ int lbm_ms_get_info(lbm_ms_t h, lbm_ms_info* info);
 /* Velocity set of a lattice: *q, e[3*q] (ex, ey, ez), w[q] (either pointer may be NULL). */
 int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w);
 
+/* The 2D step's work list for a host mask (nx*ny bytes, 1 = solid, used as given), host only:
+ * the tiles that lbm_ms_set_geometry would build for launch shape (tile_y, rows) of
+ * lbm_ms_tile_options.  *n_tiles and *n_ent receive the counts; with tiles and ent non-NULL
+ * (8 int32 per tile, n_ent uint32) the lists are copied out too, so call once for the counts and
+ * again with buffers of that size.  Per tile: x0, y0, instance (0), 0, then the offset and count
+ * of its own entries and of its halo entries in ent.  An entry packs the node's moment-tile
+ * coordinates as cy << 8 | cx, (x, y) = (x0 + cx - 1, y0 + cy - 1), with y taken periodically.
+ * E_ARG for a 3D lattice or a shape that is not compiled. */
+int lbm_ms_work_list(int lattice, int nx, int ny, const uint8_t* solid, int tile_y, int rows,
+                     int64_t* n_tiles, int64_t* n_ent, int32_t* tiles, uint32_t* ent);
+
 /* Launch shapes compiled for a lattice: writes up to cap (tile_y, chunk_z) pairs, returns the
  * count.  3D: 64 x tile_y columns marching chunk_z planes.  2D: workgroups of 32 tile_y lanes,
  * one fluid node per lane; chunk_z = 0 for fixed 64 x tile_y tiles (a denser tile is split into

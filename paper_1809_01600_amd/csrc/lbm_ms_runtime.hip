@@ -359,7 +359,7 @@ long long build_index(const std::vector<uint8_t>& solid, std::vector<int32_t>& i
 //  - rows == 0: fixed 64 x ty tiles; a tile with more than 32 ty fluid nodes is split into parts.
 //  - rows > 0: packed tiles: each 64-wide strip is cut into tiles of consecutive rows, a tile
 //    growing until one more row would exceed 32 ty fluid nodes or `rows` rows, so no tile splits
-//    and the lanes stay nearly full (at least 4 rows per tile for 32 ty >= 256).
+//    and more lanes hold a node (at least 4 rows per tile for 32 ty >= 256).
 void build_tiles_2d(int nx, int ny, int ty, int rows, const std::vector<uint8_t>& solid, int instance,
                     uint32_t ent_base, std::vector<int4>& tiles, std::vector<uint32_t>& ent)
 {
@@ -484,8 +484,8 @@ int default_tile_y(const lbm_ms_params& p)
 int default_chunk_z(const lbm_ms_params& p)
 {
     // 2D: the packed tiles' row limit.  Packed 64-wide tiles of up to 256 fluid nodes measured
-    // faster than fixed 64 x 8 tiles on every 2D workload: their lanes stay nearly full and no
-    // tile splits.  Best row limit on the 1024^2 slice: 9 for D2Q9 in every storage mode (FP32
+    // faster than fixed 64 x 8 tiles on every 2D workload: more lanes hold a node and no tile
+    // splits.  Best row limit on the 1024^2 slice: 9 for D2Q9 in every storage mode (FP32
     // 17.3 us; 12 rows 17.9, fixed 18.5), 12 for D2Q5 with global-shift or FP64 storage (FP32
     // 12.5 us; 10 rows 13.0, fixed 14.0) and 9 for D2Q5 with the NODE shift, whose staged
     // references make 12-row tiles slower than fixed ones (FP32 18.0 us; 12 rows 19.4, fixed 18.3).
@@ -730,6 +730,30 @@ int lbm_ms_clean_geometry(int lattice, int nx, int ny, int nz, const uint8_t* so
     const long long open = clean_pores(p, m);
     std::memcpy(solid_out, m.data(), N);
     if (n_open) *n_open = open;
+    return LBM_MS_OK;
+}
+
+int lbm_ms_work_list(int lattice, int nx, int ny, const uint8_t* solid, int tile_y, int rows,
+                     int64_t* n_tiles, int64_t* n_ent, int32_t* tiles, uint32_t* ent)
+{
+    if (!solid || !n_tiles || !n_ent || nx < 2 || ny < 1) return LBM_MS_E_ARG;
+    if (!known_lattice(lattice) || !is_2d(lattice) || !tile_ok(lattice, tile_y, rows)) return LBM_MS_E_ARG;
+    std::vector<uint8_t> m(solid, solid + (size_t)nx * ny);
+    for (auto& v : m) v = v ? 1 : 0;
+    std::vector<int4> tl;
+    std::vector<uint32_t> en;
+    build_tiles_2d(nx, ny, tile_y, rows, m, 0, 0, tl, en);
+    if (!tiles_in_bounds(tl, en, tile_y, rows)) return LBM_MS_E_ARG;
+    *n_tiles = (int64_t)(tl.size() / 2);
+    *n_ent = (int64_t)en.size();
+    if (tiles)
+        for (size_t t = 0; t < tl.size(); ++t) {
+            tiles[4 * t + 0] = tl[t].x;
+            tiles[4 * t + 1] = tl[t].y;
+            tiles[4 * t + 2] = tl[t].z;
+            tiles[4 * t + 3] = tl[t].w;
+        }
+    if (ent) std::memcpy(ent, en.data(), en.size() * sizeof(uint32_t));
     return LBM_MS_OK;
 }
 

@@ -107,6 +107,10 @@ _SIGNATURES = [
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                                              ctypes.POINTER(ctypes.c_uint8),
                                              ctypes.POINTER(ctypes.c_int64)]),
+    ("lbm_ms_work_list", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                        _VP, _VP]),
     ("lbm_ms_set_bc", ctypes.c_int, [_VP, _DP, ctypes.c_double]),
     ("lbm_ms_set_source", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double]),
     ("lbm_ms_init", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
@@ -203,6 +207,26 @@ def clean_geometry(lattice: str, solid: np.ndarray):
     if rc != OK:
         raise LbmMsError(rc, "clean_geometry")
     return out, int(n_open.value)
+
+
+def work_list(lattice: str, solid: np.ndarray, tile_y: int, rows: int):
+    """Host-only 2D work list of a [ny, nx] (or [1, ny, nx]) mask for launch shape (tile_y, rows):
+    (tiles int32 [T, 8], entries uint32 [E]); see lbm_ms_work_list in lbm_ms.h."""
+    solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1, solid.shape[-1])
+    ny, nx = solid.shape
+    nt, ne = ctypes.c_int64(0), ctypes.c_int64(0)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    args = (LATTICES[lattice], nx, ny, solid.ctypes.data_as(u8), int(tile_y), int(rows),
+            ctypes.byref(nt), ctypes.byref(ne))
+    rc = lib().lbm_ms_work_list(*args, None, None)
+    if rc != OK:
+        raise LbmMsError(rc, "work_list")
+    tiles = np.zeros((nt.value, 8), dtype=np.int32)
+    ent = np.zeros(max(ne.value, 1), dtype=np.uint32)
+    rc = lib().lbm_ms_work_list(*args, tiles.ctypes.data, ent.ctypes.data)
+    if rc != OK:
+        raise LbmMsError(rc, "work_list")
+    return tiles, ent[:ne.value]
 
 
 def tile_options(lattice: int, precision: int = FP32):
