@@ -17,6 +17,12 @@ Parity status of each function (what pins it is in the tests that name it):
 * ``residual``: plain definition (relative L2 change per step over a window).
 * ``paper_profile`` (initial field from the generalized Fick law at the electrode flux): pinned
   by its derivative matching Eq. 19 and by the augmented matrix exponential.
+* Velocity sets D2Q9, D3Q19, D2Q5 and D3Q7 (``velocities``): isotropy and the D1Q3 marginal, the
+  exact variance law, the discrete Stefan chain, conservation and clean-up on each.
+* ``set_source`` (Eq. 27 on a reaction layer): conservation with the source, second-order
+  convergence to the continuum profile with a distributed sink.
+* ``set_trt`` (two-relaxation-time collision): reduction to BGK when both rates agree,
+  conservation, a porous steady state independent of tau_ref.
 """
 
 from __future__ import annotations
