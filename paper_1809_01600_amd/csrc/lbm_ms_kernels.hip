@@ -845,6 +845,7 @@ static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int c
     else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
     else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
     else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
+    else if (ty == 8 && cz == 64) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 64>), dim3(nblocks), dim3(512), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -909,9 +910,9 @@ int tile_options(int lattice, int* ty, int* cz, int cap)
     // 2D: (lanes / 32, 0) for fixed 64 x TY tiles, (lanes / 32, rows) for packed tiles of at
     // most `rows` rows; 3D: (TY, planes per workgroup)
     static const int t2[5][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 9}, {8, 12}};
-    static const int t3[4][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}};
+    static const int t3[5][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}};
     const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
-    const int total = d2 ? 5 : 4;
+    const int total = 5;
     for (int i = 0; i < total && i < cap; ++i) {
         if (ty) ty[i] = d2 ? t2[i][0] : t3[i][0];
         if (cz) cz[i] = d2 ? t2[i][1] : t3[i][1];
