@@ -495,10 +495,11 @@ int default_chunk_z(const lbm_ms_params& p)
         return (p.lattice == LBM_MS_D2Q5 && !node_shift(p)) ? 12 : 9;
     }
     if (p.chunk_z > 0) return p.chunk_z;
-    // 64-plane chunks halve the per-workgroup prologue (five staged planes) and, measured on the
-    // 256^3 block with 512-lane tiles, run D3Q19 FP32 in 0.898 ms against 0.936 ms for 32
-    // planes (D3Q7 0.366 against 0.373); FP64 and the NODE modes keep 32
-    if (p.nz >= 256 && default_tile_y(p) == 8 && p.precision != LBM_MS_FP64 && !node_shift(p)) return 64;
+    // 64-plane chunks halve the per-workgroup prologue (five staged planes).  Measured on the
+    // 256^3 block with 512-lane tiles, 32 -> 64 planes: D3Q19 FP32 0.936 -> 0.898 ms, BF16
+    // 0.845 -> 0.815, FP32 NODE 1.594 -> 1.517, BF16 NODE 1.276 -> 1.247; D3Q7 FP32 0.373 ->
+    // 0.366, FP32 NODE 0.771 -> 0.754.  FP64 (not measured at 64) keeps 32.
+    if (p.nz >= 256 && default_tile_y(p) == 8 && p.precision != LBM_MS_FP64) return 64;
     return p.nz >= 128 ? 32 : 16;
 }
 

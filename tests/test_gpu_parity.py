@@ -467,3 +467,34 @@ def test_full_size_batch_conserves_species_per_instance():
         assert np.all(dout <= _outflow_tol("fp32", info)), k
         assert np.all(err <= tol), k
     b.close()
+
+
+_SHAPE_ORACLE = {}
+
+
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q7"])
+@pytest.mark.parametrize("precision,shift,tol", [("fp32", lbm_ms.SHIFT_GLOBAL, 2e-6),
+                                                 ("bf16", lbm_ms.SHIFT_GLOBAL, 2e-3),
+                                                 ("fp32", lbm_ms.SHIFT_NODE, 2e-6),
+                                                 ("bf16", lbm_ms.SHIFT_NODE, 2e-3)])
+def test_3d_launch_shapes_in_every_storage_mode(lat, precision, shift, tol):
+    """Every 3D launch shape, 64-plane chunks included (nz = 80 leaves a ragged last chunk), in
+    every storage mode against the FP64 oracle (stoichiometric ratio, uniform start; the
+    tolerances of the short-run storage tests).  Shapes are not compared bit for bit with each
+    other: the compiler may contract FP32 multiply-adds differently in each instantiation."""
+    case = inputs.random_small(70, 20, 80, lat, seed=17, solid_frac=0.2, tau_ref=4.0)
+    if lat not in _SHAPE_ORACLE:
+        o = oracle.Oracle(case, ms_mode=oracle.STOICH)
+        o.init_uniform()
+        o.step(30)
+        _SHAPE_ORACLE[lat] = o.moments()
+    Xo = _SHAPE_ORACLE[lat]
+    for ty, cz in lbm_ms.tile_options(lbm_ms.LATTICES[lat]):
+        s = lbm_ms.Solver(case, precision=precision, shift_mode=shift, tile_y=ty, chunk_z=cz,
+                          ms_mode=lbm_ms.STOICH)
+        s.init()
+        s.step(30)
+        err = float(np.max(np.abs(s.get_fields() - Xo)))
+        s.close()
+        print("%s %s shift %d tile (%d, %d): max |dX| %.3e" % (lat, precision, shift, ty, cz, err))
+        assert err <= tol, (ty, cz, err)
