@@ -846,6 +846,7 @@ static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int c
     else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
     else if (ty == 8 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 32>), dim3(nblocks), dim3(512), 0, st, a);
     else if (ty == 8 && cz == 64) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 64>), dim3(nblocks), dim3(512), 0, st, a);
+    else if (ty == 8 && cz == 128) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 128>), dim3(nblocks), dim3(512), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -910,14 +911,45 @@ int tile_options(int lattice, int* ty, int* cz, int cap)
     // 2D: (lanes / 32, 0) for fixed 64 x TY tiles, (lanes / 32, rows) for packed tiles of at
     // most `rows` rows; 3D: (TY, planes per workgroup)
     static const int t2[5][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 9}, {8, 12}};
-    static const int t3[5][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}};
+    static const int t3[6][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}, {8, 128}};
     const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
-    const int total = 5;
+    const int total = d2 ? 5 : 6;
     for (int i = 0; i < total && i < cap; ++i) {
         if (ty) ty[i] = d2 ? t2[i][0] : t3[i][0];
         if (cz) cz[i] = d2 ? t2[i][1] : t3[i][1];
     }
     return total;
+}
+
+// Workgroups of the 3D step that one CU holds at once for 64 x ty columns (the 32-plane build;
+// the chunk length does not change the register or LDS footprint), 0 on error.
+template <class L, int P, bool NS>
+static int resident3d_l(int ty)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (ty == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<L, P, NS, 4, 32>, 256, 0);
+    else if (ty == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<L, P, NS, 8, 32>, 512, 0);
+    return e == hipSuccess ? n : 0;
+}
+
+template <class L>
+static int resident3d_p(int prec, int node_shift, int ty)
+{
+    switch (prec) {
+    case P_F64: return resident3d_l<L, P_F64, false>(ty);
+    case P_F32: return node_shift ? resident3d_l<L, P_F32, true>(ty) : resident3d_l<L, P_F32, false>(ty);
+    case P_F16: return node_shift ? resident3d_l<L, P_F16, true>(ty) : resident3d_l<L, P_F16, false>(ty);
+    case P_BF16: return node_shift ? resident3d_l<L, P_BF16, true>(ty) : resident3d_l<L, P_BF16, false>(ty);
+    }
+    return 0;
+}
+
+int step3d_resident_blocks(int lattice, int prec, int node_shift, int ty)
+{
+    if (lattice == 1) return resident3d_p<D3Q19>(prec, node_shift, ty);
+    if (lattice == 3) return resident3d_p<D3Q7>(prec, node_shift, ty);
+    return 0;
 }
 
 hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,

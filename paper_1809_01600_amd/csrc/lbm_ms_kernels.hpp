@@ -8,6 +8,8 @@
 namespace lbmms {
 
 int tile_options(int lattice, int* ty, int* cz, int cap);
+// workgroups of the 3D step (64 x ty columns) resident per CU on the current device, 0 on error
+int step3d_resident_blocks(int lattice, int prec, int node_shift, int ty);
 hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,
                        int ty, int cz, int nblocks);
 // 2D work-list step: insts = instance table of this step's parity, tiles = 2 int4 per tile;

@@ -495,11 +495,24 @@ int default_chunk_z(const lbm_ms_params& p)
         return (p.lattice == LBM_MS_D2Q5 && !node_shift(p)) ? 12 : 9;
     }
     if (p.chunk_z > 0) return p.chunk_z;
-    // 64-plane chunks halve the per-workgroup prologue (five staged planes).  Measured on the
-    // 256^3 block with 512-lane tiles, 32 -> 64 planes: D3Q19 FP32 0.936 -> 0.898 ms, BF16
-    // 0.845 -> 0.815, FP32 NODE 1.594 -> 1.517, BF16 NODE 1.276 -> 1.247; D3Q7 FP32 0.373 ->
-    // 0.366, FP32 NODE 0.771 -> 0.754.  FP64 (not measured at 64) keeps 32.
-    if (p.nz >= 256 && default_tile_y(p) == 8 && p.precision != LBM_MS_FP64) return 64;
+    // Longer chunks spread each workgroup's prologue (five staged planes) over more planes, as
+    // long as the grid still fills every resident workgroup slot: the largest of 128, 64 and 32
+    // planes that does.  Measured on the 256^3 block with 512-lane tiles (32 -> 64 -> 128
+    // planes): D3Q19 FP32 0.936 -> 0.898 -> 0.881 ms, BF16 0.845 -> 0.814 -> 0.797, FP32 NODE
+    // 1.594 -> 1.519 -> 1.468; D3Q7 FP32 NODE 0.771 -> 0.757 -> 0.724.  D3Q7 FP32 holds two
+    // workgroups per CU, so 128 planes (256 workgroups) leave half the slots empty: 0.371 ms at
+    // 64 against 0.457 at 128.  FP64 (not measured beyond 32) keeps the rule below.
+    const int ty = default_tile_y(p);
+    if (ty == 8 && p.precision != LBM_MS_FP64) {
+        int dev = 0, cus = 0;
+        const int per_cu = step3d_resident_blocks(p.lattice, p.precision, node_shift(p) ? 1 : 0, ty);
+        if (per_cu > 0 && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            const long long cols = (long long)((p.nx + 63) / 64) * ((p.ny + ty - 1) / ty);
+            for (int cz : {128, 64})
+                if (cols * ((p.nz + cz - 1) / cz) >= (long long)per_cu * cus) return cz;
+        }
+    }
     return p.nz >= 128 ? 32 : 16;
 }
 
