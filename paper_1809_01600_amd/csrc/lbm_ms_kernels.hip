@@ -287,8 +287,13 @@ __device__ inline void gather3d(const StepArgs& a, int i, const int (&si)[L::Q],
 // plane moments (tile + halo ring), z gradients from the column's own rolling registers.  One
 // barrier per plane.
 // ---------------------------------------------------------------------------------------------
+// D3Q7 with global-shift storage fits 128 VGPRs: ask for four waves per SIMD (the second
+// launch-bounds argument counts waves per SIMD)
+template <class L, int P, bool NS, int TY>
+constexpr int step3d_min_waves() { return (std::is_same<L, D3Q7>::value && !NS && P != P_F64 && TY == 8) ? 4 : 1; }
+
 template <class L, int P, bool NS, int TY, int CZ>
-__global__ __launch_bounds__(64 * TY) void k_step3d(StepArgs a)
+__global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k_step3d(StepArgs a)
 {
     using CT = typename Codec<P>::CT;
     constexpr int TX = 64, RX = TX + 4, RY = TY + 4, NPL = 5;

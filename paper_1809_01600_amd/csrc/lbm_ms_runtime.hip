@@ -473,11 +473,10 @@ int default_tile_y(const lbm_ms_params& p)
     if (p.tile_y > 0) return p.tile_y;
     if (is_2d(p.lattice)) return p.ny >= 8 ? 8 : 4;
     // measured on a 256^3 porous block: D3Q19 FP64 runs best with the 256-lane tiles (its
-    // 512-lane build spills), every other D3Q19 mode with the 512-lane ones.  D3Q7 builds without
-    // spills; with 16-bit storage its 512-lane build needs 129 VGPRs (three waves per SIMD) and
-    // the 256-lane tiles are faster (0.375 against 0.467 ms for BF16)
-    const bool b16 = p.precision == LBM_MS_FP16 || p.precision == LBM_MS_BF16;
-    if (p.lattice == LBM_MS_D3Q7) return b16 ? 4 : 8;
+    // 512-lane build spills), every other mode, D3Q7 included, with the 512-lane ones (D3Q7
+    // with 16-bit storage is built for four waves per SIMD: BF16 0.339 ms against 0.369 ms on
+    // 256-lane tiles)
+    if (p.lattice == LBM_MS_D3Q7) return 8;
     return p.precision == LBM_MS_FP64 ? 4 : 8;
 }
 
