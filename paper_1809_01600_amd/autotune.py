@@ -1,16 +1,20 @@
 """Launch-shape autotuner: times every compiled tile shape on the problem at hand and keeps the
-fastest, cached per (lattice, precision, shift, box size) in a JSON file.
+fastest, cached in a JSON file per (lattice, precision, shift, problem size), keyed also on the
+built library's contents and the device name, so a rebuilt kernel or another GPU re-tunes.
 
     from paper_1809_01600_amd import autotune
     best = autotune.tune(solver)          # lbm_ms.Solver
     best = autotune.tune_batch(batch)     # lbm_ms.Batch
 
 The cache lives at $LBM_MS_TUNE_CACHE (default ~/.cache/lbm_ms_tune.json).  Tuning changes only
-the launch shape; results are bitwise identical across shapes for a given storage precision.
+the launch shape.  In FP64 and in 2D the results do not depend on it; 3D instantiations of
+different shapes may contract FP32 multiply-adds differently, so FP32 and 16-bit 3D results can
+differ between shapes in the last bits (within the FP32 parity tolerance).
 """
 
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
@@ -47,8 +51,29 @@ def _lattice_name(code):
     return next(name for name, c in lbm_ms.LATTICES.items() if c == code)
 
 
+_BUILD_ID = None
+
+
+def _build_id() -> str:
+    """Hash of the loaded library file plus the device name."""
+    global _BUILD_ID
+    if _BUILD_ID is None:
+        h = hashlib.sha256()
+        with open(lbm_ms.LIB_PATH, "rb") as f:
+            h.update(f.read())
+        try:
+            import torch
+            dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+            name = "%s/%s" % (dev.name, getattr(dev, "gcnArchName", ""))
+        except Exception:
+            name = "unknown-device"
+        _BUILD_ID = h.hexdigest()[:16] + "|" + name
+    return _BUILD_ID
+
+
 def _key(kind, lattice, precision, shift, dims):
-    return "%s|%s|p%d|s%d|%s" % (kind, lattice, precision, shift, "x".join(str(d) for d in dims))
+    return "%s|%s|p%d|s%d|%s|%s" % (kind, lattice, precision, shift,
+                                    "x".join(str(d) for d in dims), _build_id())
 
 
 def tune(solver, steps: int = 100, warmup: int = 10, use_cache: bool = True):
@@ -82,8 +107,9 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
     inlet composition and advances it; initialize again before a solve."""
     p = batch.params
     sizes = sorted((c.nx, c.ny) for c in batch.cases)
+    size_list = hashlib.sha256(repr(sizes).encode()).hexdigest()[:12]
     key = _key("batch", _lattice_name(p.lattice), p.precision, p.shift_mode,
-               (len(sizes), sum(a * b for a, b in sizes)))
+               (len(sizes), sum(a * b for a, b in sizes), size_list))
     data = _load() if use_cache else {}
     if key in data:
         batch.set_tile(*data[key]["tile"])

@@ -137,15 +137,16 @@ __device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[L::Q],
 // nodes it needs as halo.  One node per lane keeps the register count low enough for eight
 // waves per SIMD.
 // ---------------------------------------------------------------------------------------------
-// Global-shift FP32 and 16-bit instantiations fit in 64 VGPRs: ask for eight waves per SIMD
-// (minimum workgroups per CU = 8 waves x 4 SIMDs / (TY / 2) waves per workgroup).
+// Global-shift FP32 and 16-bit instantiations fit in 64 VGPRs: ask for eight waves per SIMD for
+// every tile height.  (HIP passes the second launch-bounds argument to the compiler as the
+// minimum number of waves per SIMD, not as CUDA's workgroups per multiprocessor.)
 template <int P, bool NS>
-constexpr int step2d_min_blocks(int ty) { return (P != P_F64 && !NS) ? 64 / ty : 1; }
+constexpr int step2d_min_waves() { return (P != P_F64 && !NS) ? 8 : 1; }
 
 // TYR: rows of the staged region and moment tile.  TYR = TY for fixed 64 x TY tiles; a larger
 // TYR for packed tiles, which the host grows row by row up to TYR rows or 32 TY fluid nodes.
 template <class L, int P, bool NS, int TY, int TYR>
-__global__ __launch_bounds__(32 * TY, (step2d_min_blocks<P, NS>(TY))) void k_step2d(const StepArgs* __restrict__ insts,
+__global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d(const StepArgs* __restrict__ insts,
                                                     const int4* __restrict__ tiles,
                                                     const unsigned* __restrict__ ent)
 {

@@ -973,14 +973,16 @@ int lbm_ms_residual(lbm_ms_t h, double* residual)
     h->snap_step = h->steps;
     const double r = (K > 0 && v[1] > 0) ? std::sqrt(v[0]) / ((double)K * std::sqrt(v[1])) : 0.0;
     *residual = r;
+    // the clamp flag covers one check window: clear it whatever this check reports
+    if (clamp) {
+        rc = h->hip(hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream), "clamp flag reset");
+        if (rc) return rc;
+    }
     if (v[4] > 0 || !std::isfinite(r))
         return h->fail(LBM_MS_E_DIVERGED, "%.0f nodes with non-finite mole fractions", v[4]);
     if (v[5] > 0)
         return h->fail(LBM_MS_E_NEG_FRACTION, "%.0f nodes with a mole fraction below -1e-12", v[5]);
-    if (clamp) {
-        hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream);
-        return h->fail(LBM_MS_E_TAU_CLAMP, "a relaxation time hit the clamp");
-    }
+    if (clamp) return h->fail(LBM_MS_E_TAU_CLAMP, "a relaxation time hit the clamp");
     return LBM_MS_OK;
 }
 
