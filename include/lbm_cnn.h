@@ -54,6 +54,18 @@ int lbm_cnn_masked_mse(const float* pred, const float* target, const float* flui
                        int H, int W, float* grad, double* loss_out, double* partial,
                        void* stream);
 
+/* lbm_cnn_masked_mse without the partial argument, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs and results as lbm_cnn_masked_mse (bitwise: the same kernels in the
+ * same order).  Its scratch is a fixed library array of 2 * 1024 + 1 float64 (16 KiB) per
+ * device, held until the process ends; the call allocates nothing.  The partial-sum count is
+ * set by the grid, at most 1024 workgroups, so every size fits: -8 (LBM_MS_E_NOMEM) would mean
+ * the fixed scratch is too small; -1 for null pointers or non-positive sizes, -4 for a HIP
+ * error.  All calls on one device share that device's scratch: calls that overlap in time on
+ * one device (different streams or host threads) race and must be serialized by the caller. */
+int lbm_cnn_masked_mse_noalloc(const float* pred, const float* target, const float* fluid, int B,
+                               int C, int H, int W, float* grad, double* loss_out, void* stream);
+
 /* Adam update of n parameters (step t >= 1). */
 int lbm_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
                  float beta1, float beta2, float eps, int t, void* stream);

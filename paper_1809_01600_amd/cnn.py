@@ -39,6 +39,7 @@ _CNN_SIGNATURES = [
     ("lbm_cnn_backward_weight_scratch", ctypes.c_size_t, [_I, _I, _I, _I, _I]),
     ("lbm_cnn_conv_backward_weight", _I, [_VP, _VP, _VP, _I, _I, _I, _I, _I, _VP, _VP, _VP, _VP]),
     ("lbm_cnn_masked_mse", _I, [_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP]),
+    ("lbm_cnn_masked_mse_noalloc", _I, [_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP, _VP]),
     ("lbm_cnn_adam", _I, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, ctypes.c_float, _I, _VP]),
     ("lbm_cnn_to_bf16", _I, [_VP, _VP, ctypes.c_int64, _VP]),
@@ -225,3 +226,16 @@ def assemble(pred, base, x_min=1e-6):
 def targets(X, base):
     """Training targets (X_s - base_s) / SCALE for s = 1, 2 (torch, device)."""
     return ((X[:, :2] - base[:, :, None, :]) / SCALE).float().contiguous()
+
+
+def masked_mse_noalloc(pred, target, fluid, grad, loss):
+    """Masked MSE and its gradient into caller-provided device tensors (contiguous float32 pred,
+    target, grad [B,C,H,W], fluid [B,H,W], loss: one float64), using the library's fixed scratch:
+    nothing is allocated by this call."""
+    B, C, H, W = pred.shape
+    for t in (pred, target, fluid, grad, loss):
+        if not t.is_contiguous():
+            raise ValueError("masked_mse_noalloc takes contiguous tensors")
+    _ok(lib().lbm_cnn_masked_mse_noalloc(_p(pred), _p(target), _p(fluid), B, C, H, W, _p(grad),
+                                         _p(loss), _stream()), "mse (no alloc)")
+    return loss, grad

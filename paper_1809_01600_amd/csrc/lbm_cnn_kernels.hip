@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lbm_cnn.h"
 
 namespace lbmcnn {
@@ -465,6 +467,62 @@ int lbm_cnn_masked_mse(const float* pred, const float* target, const float* flui
     e = status(hipGetLastError());
     if (e) return e;
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, st, grad, n, partial + 2 * 1024);
+    return status(hipGetLastError());
+}
+
+// Scratch of lbm_cnn_masked_mse_noalloc: the same 2 * 1024 + 1 float64 that lbm_cnn_masked_mse
+// takes as `partial` (two sums per pass-1 workgroup, at most 1024 workgroups, then 1 / count).
+// One copy per device, held until the process ends.  Host code never passes this name to a
+// kernel: its device address comes from hipGetSymbolAddress, once per device.
+constexpr int MSE_SCRATCH_DOUBLES = 2 * 1024 + 1;
+static __device__ __align__(256) double scratch[MSE_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES];
+
+// device address of `scratch` on the current device (nullptr and *err set on failure)
+static double* scratch_address(int* err)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        *err = -4;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            *err = -4;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+int lbm_cnn_masked_mse_noalloc(const float* pred, const float* target, const float* fluid, int B,
+                               int C, int H, int W, float* grad, double* loss_out, void* stream)
+{
+    if (!pred || !target || !fluid || !grad || !loss_out || B <= 0 || C <= 0 || H <= 0 || W <= 0)
+        return -1;
+    const long long n = (long long)B * C * H * W;
+    const int g = grid_for(n, 256, 1024);
+    // pass 1 writes 2 g partial sums, pass 2 one more value: the fixed scratch must hold them
+    if (2 * (long long)g + 1 > MSE_SCRATCH_DOUBLES) return -8;
+    int err = 0;
+    double* part = scratch_address(&err);
+    if (!part) return err;
+    hipStream_t st = (hipStream_t)stream;
+    // every slot that pass 2 reads is written by pass 1 of this call: nothing to clear
+    hipLaunchKernelGGL(k_masked_mse, dim3(g), dim3(256), 0, st, pred, target, fluid, B, C, H, W,
+                       grad, part);
+    int e = status(hipGetLastError());
+    if (e) return e;
+    hipLaunchKernelGGL(k_mse_finalize, dim3(1), dim3(64), 0, st, part, g, loss_out, part + 2 * 1024);
+    e = status(hipGetLastError());
+    if (e) return e;
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, st, grad, n, part + 2 * 1024);
     return status(hipGetLastError());
 }
 
