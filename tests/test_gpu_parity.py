@@ -293,14 +293,15 @@ def test_full_size_porous_2d_fp64_and_fp32():
 
 @pytest.mark.parametrize("precision,x_tol,eta_tol", [
     ("fp32", 1e-7, 1e-8),
-    ("bf16", 2e-4, 2e-5),
-    ("fp16", 2e-4, 2e-5),
+    ("bf16", 1e-5, 1e-6),
+    ("fp16", 1e-5, 1e-6),
 ])
 def test_node_shift_steady_state_matches_fp64(precision, x_tol, eta_tol):
     """Steady state of the reduced-precision NODE-shift storage against the FP64 path (itself
-    pinned to the oracle above).  The moment stays in FP64, so the rounding of the stored
-    deviations does not stall the slowest mode: the converged fields agree far below the
-    distance to steady state that a residual of 1e-8 leaves."""
+    pinned to the oracle's steady state in test_gpu_steady.py).  The moment stays in FP64, so
+    the rounding of the stored deviations does not stall the slowest mode: the converged fields
+    agree to 1e-5 in mole fraction, far below the distance to steady state that a residual of
+    1e-8 leaves."""
     case = _percolating_2d(64, 40, seed0=31, tau_ref=3.0, j_A_cm2=1.5)
     ref = lbm_ms.Solver(case, precision="fp64", ms_mode=lbm_ms.STOICH)
     ref.init()

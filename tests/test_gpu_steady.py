@@ -1,0 +1,143 @@
+"""Converged steady states on the GPU against the oracle and against closed forms.
+
+* A stable fixed point does not amplify rounding: after the same number of steps, well past
+  convergence, the GPU's FP64 steady state of a porous slice equals the oracle's to within the
+  rounding floor of a contraction, ulp / lambda (about 1e-12 here: lambda is about 2e-4 per
+  step), under the paper's local flux-norm ratio (Eq. 24) as well as the stoichiometric one.
+* The Stefan tube (128 x 8, 5000 steps) against the continuum Stefan solution of Eq. 19 (the
+  augmented matrix exponential): after 5000 steps the transient still amounts to about 4e-7 in X
+  (measured with the oracle: 3.7e-7 local, 4.6e-7 stoichiometric); converged, the lattice
+  differs from the continuum by its second-order discretization error, 5e-11 at 128 nodes
+  (1.8e-10 at 64, 1.1e-11 at 256).
+"""
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+from paper_1809_01600_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_01600_amd import lbm_ms  # noqa: E402
+
+STEADY_STEPS = 200_000  # about 46 / lambda for the small slice below
+
+
+def _percolating_2d(n, ny, seed0=0, **kw):
+    seed = seed0
+    while True:
+        c = inputs.porous_2d(n=n, ny=ny, seed=seed, **kw)
+        if oracle.label("D2Q9", c.mask())[1] > 0:
+            return c
+        seed += 1
+
+
+_ORACLE_STEADY = {}
+
+
+def _oracle_steady(case, mode):
+    key = (case.seed, case.nx, case.ny, mode)
+    if key not in _ORACLE_STEADY:
+        o = oracle.Oracle(case, ms_mode=mode)
+        o.init_uniform()
+        o.step(STEADY_STEPS)
+        _ORACLE_STEADY[key] = (o.moments(), o.overpotential(), o.fluid())
+    return _ORACLE_STEADY[key]
+
+
+SMALL = dict(n=40, ny=24, seed0=31, tau_ref=3.0, j_A_cm2=1.5)
+
+
+@pytest.mark.parametrize("mode", [lbm_ms.LOCAL_FLUX, lbm_ms.STOICH], ids=["local", "stoich"])
+def test_converged_fp64_steady_state_equals_the_oracles(mode):
+    case = _percolating_2d(**SMALL)
+    print("steady parity case seed %d mode %d" % (case.seed, mode), flush=True)
+    Xo, eta_o, fl = _oracle_steady(case, mode)
+    s = lbm_ms.Solver(case, precision="fp64", ms_mode=mode)
+    s.init()
+    s.step(STEADY_STEPS - 1000)
+    s.residual()  # a fresh window: the last 1000 steps
+    s.step(1000)
+    r = s.residual()
+    X = s.get_fields()
+    err = np.max(np.abs(X - Xo)[:2][:, fl])
+    deta = abs(s.overpotential() - eta_o)
+    print("converged FP64 vs oracle: r %.2e, max |dX| %.2e, |d eta| %.2e V" % (r, err, deta))
+    assert r < 1e-14  # converged: the state no longer moves
+    assert err <= 1e-12
+    assert deta <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("precision,x_tol,eta_tol", [
+    ("fp32", 1e-7, 1e-8),
+    ("fp16", 1e-5, 1e-6),
+    ("bf16", 1e-5, 1e-6),
+])
+def test_node_shift_steady_state_matches_the_oracle(precision, x_tol, eta_tol):
+    """The reduced-precision NODE-shift storage converged on the small slice against the oracle's
+    steady state, local flux-norm ratio: 1e-5 in mole fraction for the 16-bit modes."""
+    case = _percolating_2d(**SMALL)
+    Xo, eta_o, fl = _oracle_steady(case, lbm_ms.LOCAL_FLUX)
+    s = lbm_ms.Solver(case, precision=precision, shift_mode=lbm_ms.SHIFT_NODE,
+                      ms_mode=lbm_ms.LOCAL_FLUX)
+    s.init()
+    s.step(STEADY_STEPS)
+    X = s.get_fields()
+    err = np.max(np.abs(X - Xo)[:2][:, fl])
+    deta = abs(s.overpotential() - eta_o)
+    print("%s NODE vs oracle steady state: max |dX| %.2e, |d eta| %.2e V" % (precision, err, deta))
+    assert err <= x_tol and deta <= eta_tol
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [lbm_ms.LOCAL_FLUX, lbm_ms.STOICH], ids=["local", "stoich"])
+def test_stefan_tube_against_the_continuum_closed_form(mode):
+    case = inputs.stefan_tube()  # 128 x 8, 2 mm, j = 0.5 A/cm^2, tau_ref = 50
+    I = case.j_A_cm2 * 1e4
+    N = np.array([-case.nu[s] * I / (case.n_electrons * cf.FARADAY) for s in range(3)])
+    xs = np.arange(case.nx) * case.dx  # node k sits k dx from the inlet node (Dirichlet on node 0)
+    C = cf.stefan_continuum(case.D_matrix(), case.T, case.p, case.X_in, N, xs)
+    s = lbm_ms.Solver(case, precision="fp64", ms_mode=mode)
+    s.init()
+    s.step(5000)
+    X = s.get_fields()[:, 0]  # [3, ny, nx]
+    err5k = np.max(np.abs(X[:2] - C[:2, None, :]))
+    s.step(60_000)
+    X = s.get_fields()[:, 0]
+    err = np.max(np.abs(X[:2] - C[:2, None, :]))
+    # eta from the continuum outlet composition (Eq. 43)
+    eta_c = cf.overpotential(case.T, case.n_electrons, case.X_in, C[:, -1])
+    deta = abs(s.overpotential() - eta_c)
+    print("Stefan tube vs closed form: 5000 steps %.2e, converged %.2e, |d eta| %.2e V"
+          % (err5k, err, deta))
+    assert err5k <= 1e-6
+    assert err <= 1e-10
+    assert deta <= 1e-9 * abs(eta_c) + 1e-12
+
+
+@pytest.mark.parametrize("precision", [
+    "fp16",
+    pytest.param("bf16", marks=pytest.mark.xfail(
+        strict=True, reason="BF16's 8-bit significand leaves the 128^2 steady states about "
+                            "3.6e-5 from FP64 in X, above the 1e-5 target; FP16 (scaled) meets it")),
+])
+def test_node_shift_steady_states_of_the_precision_study(precision):
+    """The eight 128^2 porous slices of the precision study (C4-like geometry, X_in ~
+    Dirichlet(6, 3, 1), tau_ref 3, stoichiometric ratio), batched, converged to r = 1e-10:
+    16-bit NODE-shift storage against FP64 storage (itself pinned to the oracle above), 1e-5 in
+    mole fraction and 1e-6 V in eta."""
+    from paper_1809_01600_amd import warmstart
+    print("precision study", precision, flush=True)
+    res = warmstart.precision_study(n=8, side=128, tol=1e-10, max_steps=1_500_000,
+                                    modes=[precision + "_node"], log=lambda m: print(m, flush=True))
+    rec = res[precision + "_node"]
+    assert all(st == 0 for st in rec["status"]), rec["status"]
+    assert rec["max_abs_dX"] <= 1e-5, rec["max_abs_dX"]
+    assert rec["max_abs_deta_V"] <= 1e-6, rec["max_abs_deta_V"]
