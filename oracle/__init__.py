@@ -63,6 +63,7 @@ class _Params(ctypes.Structure):
         ("tau_min", ctypes.c_double), ("tau_max", ctypes.c_double),
         ("S", ctypes.c_double * 2), ("src_x0", ctypes.c_int),
         ("trt", ctypes.c_int), ("lambda_trt", ctypes.c_double),
+        ("tau_flow", ctypes.c_double),
     ]
 
 
@@ -103,6 +104,13 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.POINTER(_Params), u8p, dp, dp]
         L.orc_label.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p, u8p]
         L.orc_label.restype = ctypes.c_long
+        L.orc_step_adv.argtypes = [ctypes.POINTER(_Params), u8p, dp, dp, dp, dp, dp, dp,
+                                   ctypes.POINTER(_Stats)]
+        L.orc_run_adv.argtypes = [ctypes.POINTER(_Params), u8p, dp, dp, dp, dp, dp, ctypes.c_long,
+                                  ctypes.POINTER(_Stats)]
+        L.orc_collide_adv.argtypes = [ctypes.POINTER(_Params), u8p, dp, dp, dp, dp, dp, dp, dp,
+                                      ctypes.POINTER(_Stats)]
+        L.orc_flow_rest.argtypes = [ctypes.POINTER(_Params), u8p, dp]
         L.orc_num_velocities.argtypes = [ctypes.c_int]
         L.orc_velocities.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
         _lib = L
@@ -175,7 +183,8 @@ class Oracle:
     def __init__(self, case, ms_mode: int = LOCAL_FLUX, inlet_wall: bool = False,
                  eps: Optional[float] = None, tau_min: float = 0.5 + 1.0e-9,
                  tau_max: float = 1.0e6,
-                 clean_geometry: bool = True, Q_override=None):
+                 clean_geometry: bool = True, Q_override=None, advection: bool = False,
+                 tau_flow: float = 1.0):
         self.case = case
         self.lattice = case.lattice
         mask = case.mask()
@@ -208,9 +217,14 @@ class Oracle:
         p.tau_min, p.tau_max = tau_min, tau_max
         p.S[0], p.S[1], p.src_x0 = 0.0, 0.0, case.nx  # no volumetric source
         p.trt, p.lambda_trt = 0, 0.25  # BGK unless set_trt
+        p.tau_flow = tau_flow
         self.p = p
         self.N = case.nx * case.ny * case.nz
         self.f = np.zeros((2, self.q) + case.shape)
+        # advective coupling (Eq. 26): the velocity model's populations, at rest until init
+        self.advection = advection
+        self.g = np.zeros((self.q,) + case.shape) if advection else None
+        self.uprev = np.zeros((3,) + case.shape) if advection else None  # u of the last step
         self.t = 0
         self.last = _Stats()
 
@@ -250,16 +264,26 @@ class Oracle:
         self.init_field(X0)
 
     def init_field(self, X0: np.ndarray):
+        """Equilibrium populations of X0 at rest (the velocity model, if any, at rho = 1, u = 0)."""
         X0 = np.ascontiguousarray(X0, dtype=np.float64)
         lib().orc_equilibrium(ctypes.byref(self.p), _u8(self.solid), _dp(X0), _dp(self.f))
+        if self.advection:
+            lib().orc_flow_rest(ctypes.byref(self.p), _u8(self.solid), _dp(self.g))
+            self.uprev[...] = 0.0
         self.t = 0
 
     # -- stepping -----------------------------------------------------------------------------
     def step(self, n: int = 1):
         work = np.empty_like(self.f)
         st = _Stats()
-        rc = lib().orc_run(ctypes.byref(self.p), _u8(self.solid), _dp(self.f), _dp(work), n,
-                           ctypes.byref(st))
+        if self.advection:
+            gwork = np.empty_like(self.g)
+            rc = lib().orc_run_adv(ctypes.byref(self.p), _u8(self.solid), _dp(self.f),
+                                   _dp(self.g), _dp(self.uprev), _dp(work), _dp(gwork), n,
+                                   ctypes.byref(st))
+        else:
+            rc = lib().orc_run(ctypes.byref(self.p), _u8(self.solid), _dp(self.f), _dp(work), n,
+                               ctypes.byref(st))
         if rc != 0:
             raise MemoryError("oracle step failed (%d)" % rc)
         self.t += n
@@ -277,6 +301,24 @@ class Oracle:
         X = np.empty((3,) + self.case.shape)
         lib().orc_moments(ctypes.byref(self.p), _u8(self.solid), _dp(f), _dp(X))
         return X
+
+    def collide_adv(self):
+        """Advective coupling: (post-collision species populations, post-collision velocity
+        populations, tau [2,...], u_M [3,...] in lattice units (the two-step mean the species
+        see), clamp hits) of the state."""
+        fstar = np.empty_like(self.f)
+        gstar = np.empty_like(self.g)
+        tau = np.empty((2,) + self.case.shape)
+        u = np.empty((3,) + self.case.shape)
+        st = _Stats()
+        lib().orc_collide_adv(ctypes.byref(self.p), _u8(self.solid), _dp(self.f), _dp(self.g),
+                              _dp(self.uprev), _dp(fstar), _dp(gstar), _dp(tau), _dp(u),
+                              ctypes.byref(st))
+        return fstar, gstar, tau, u, int(st.clamp_hits)
+
+    def velocity(self) -> np.ndarray:
+        """Molar-averaged velocity u_M [3, nz, ny, nx] of the velocity model (lattice units)."""
+        return self.collide_adv()[3]
 
     def collide(self):
         """(post-collision populations, tau [2,...], J [2,3,...], clamp hits) of the state."""

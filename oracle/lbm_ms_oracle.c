@@ -50,6 +50,7 @@ typedef struct {
     int src_x0;
     int trt;              /* 1: two-relaxation-time collision instead of BGK */
     double lambda_trt;    /* TRT: (tau_even - 1/2)(tau - 1/2), tau from Eq. 25 */
+    double tau_flow;      /* advective coupling only: relaxation time of the velocity model */
 } orc_params;
 
 typedef struct {
@@ -527,3 +528,283 @@ long orc_label(int lattice, int nx, int ny, int nz, const uint8_t* solid_in, uin
     free(queue);
     return outlet;
 }
+
+/*
+ * ---------------------------------------------------------------------------------------------
+ * Advective coupling (Sec. 3.1, Eq. 20-21 and 26): when the electrode reaction changes the number
+ * of moles (nu_1 + nu_2 != 0), the total flux N_t = C_t u_M no longer vanishes and the species
+ * equilibrium carries the molar-averaged velocity, f_eq = w_a X_s (1 + e_a . u_M / c_s^2) (Eq. 26
+ * divided by the constant C_t).  u_M comes from a second lattice Boltzmann model, an
+ * incompressible one whose density is the total concentration (Sec. 3.1, last paragraphs); here
+ * its Stokes limit, g_eq = w_a (rho + e_a . u / c_s^2) with rho = C_t / C_t,ref = 1 + O(Ma^2),
+ * u = sum_a e_a g_a, BGK with relaxation time tau_flow.  Its boundaries mirror the species ones:
+ * no-slip half-way bounce-back on solid, the inlet (channel) at rho = 1 by the anti-bounce-back
+ * rule, and at each open outlet node the net outflow Q_t = Q_1 + Q_2 (the electrode's total
+ * molar flux in lattice units) by the same exact-flux rule.  This linear model carries an
+ * undamped period-2 mode: populations at their equilibrium (so no collision acts on them) whose
+ * node velocity alternates between neighbouring nodes and between consecutive steps while every
+ * link flux stays uniform.  The species therefore see the mean of the node velocity over the last
+ * two steps, u_M = (u^t + u^{t-1}) / 2, which removes that mode exactly and equals u at a steady
+ * state.
+ *
+ * With advection the species populations carry N_s = X_s N_t + J_s, so the relaxation time must
+ * reproduce the diffusive flux J_s = N_s - X_s N_t (Eq. 20) alone: Eq. 24 is read with J in place
+ * of N (Eq. 19 holds with either), and the inert species now has J_3 = -J_1 - J_2 != 0.  The
+ * flux ratio J_j / J_i of two vectors is read as the projection (J_j . J_i) / |J_i|^2, which is
+ * the signed-norm rule of Eq. 24 for collinear fluxes; the regularization pulls it towards the
+ * one-dimensional steady ratio (Nh_j - X_j Nh_t) / (Nh_i - X_i Nh_t), Nh_s = -nu_s, which is also
+ * the stoichiometric variant.  At the outlet column Eq. 37's gradient uses the diffusive boundary
+ * flux J_s = Q_s - X_s Q_t.  With nu_1 + nu_2 = 0 every step reduces to the equimolar method.
+ * ---------------------------------------------------------------------------------------------
+ */
+
+/* the one-dimensional steady ratio J_j / J_i of diffusive fluxes for stoichiometric N */
+static double stoich_ratio_adv(const orc_params* p, const double X[3], int i, int j)
+{
+    const double nt = -(p->nu[0] + p->nu[1] + p->nu[2]);
+    return (-p->nu[j] - X[j] * nt) / (-p->nu[i] - X[i] * nt);
+}
+
+static int collide_adv(const orc_params* p, const orc_lattice* L, const uint8_t* solid,
+                       const double* f, const double* g, const double* uprev, double* fstar,
+                       double* gstar, double* ucur, double* tau_out, double* u_out,
+                       long* clamp_hits)
+{
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int q = L->q;
+    const int dims = (p->lattice == 1 || p->lattice == 3) ? 3 : 2;
+    const double Qt = p->Q[0] + p->Q[1];
+    double* X = (double*)malloc(sizeof(double) * 3 * N);
+    if (!X) return -8;
+    orc_moments(p, solid, f, X);
+    long hits = 0;
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const long n = node_index(p, x, y, z);
+                if (solid[n]) {
+                    for (int a = 0; a < q; ++a) {
+                        fstar[(long)a * N + n] = fstar[((long)q + a) * N + n] = 0.0;
+                        gstar[(long)a * N + n] = 0.0;
+                    }
+                    for (int d = 0; d < 3; ++d) {
+                        if (ucur) ucur[(long)d * N + n] = 0.0;
+                        if (u_out) u_out[(long)d * N + n] = 0.0;
+                    }
+                    continue;
+                }
+                /* velocity model moments */
+                double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < q; ++a) {
+                    const double ga = g[(long)a * N + n];
+                    rho += ga;
+                    for (int d = 0; d < 3; ++d) u[d] += L->e[a][d] * ga;
+                }
+                /* the species see the two-step mean (removes the period-2 mode) */
+                double um[3];
+                for (int d = 0; d < 3; ++d) {
+                    if (ucur) ucur[(long)d * N + n] = u[d];
+                    um[d] = 0.5 * (u[d] + uprev[(long)d * N + n]);
+                    if (u_out) u_out[(long)d * N + n] = um[d];
+                }
+                double Xn[3] = {X[n], X[N + n], X[2 * N + n]};
+                double B[2][2];
+                ms_matrix(p, Xn, B);
+                /* gradients, as in the equimolar method except Eq. 37's diffusive boundary flux */
+                double gr[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                for (int d = 0; d < dims; ++d) {
+                    if (d == 0 && x == p->nx - 1) {
+                        const double J0 = p->Q[0] - Xn[0] * Qt, J1 = p->Q[1] - Xn[1] * Qt;
+                        for (int s = 0; s < 2; ++s) gr[s][0] = -(B[s][0] * J0 + B[s][1] * J1);
+                        continue;
+                    }
+                    int up[3] = {x, y, z}, dn[3] = {x, y, z};
+                    up[d] += 1;
+                    dn[d] -= 1;
+                    int fu = is_fluid(p, solid, up[0], up[1], up[2]);
+                    int fd = is_fluid(p, solid, dn[0], dn[1], dn[2]);
+                    for (int s = 0; s < 2; ++s) {
+                        double xc = X[(long)s * N + n];
+                        double xu = fu ? X[(long)s * N + node_index(p, up[0], wrap(up[1], p->ny), wrap(up[2], p->nz))] : 0.0;
+                        double xd = fd ? X[(long)s * N + node_index(p, dn[0], wrap(dn[1], p->ny), wrap(dn[2], p->nz))] : 0.0;
+                        if (fu && fd) gr[s][d] = 0.5 * (xu - xd);
+                        else if (fu) gr[s][d] = xu - xc;
+                        else if (fd) gr[s][d] = xc - xd;
+                        else gr[s][d] = 0.0;
+                    }
+                }
+                /* diffusive fluxes: generalized Fick (Eq. 34), J_3 by the zero sum of Eq. 20 */
+                double det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+                double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                for (int d = 0; d < dims; ++d) {
+                    J[0][d] = -(B[1][1] * gr[0][d] - B[0][1] * gr[1][d]) / det;
+                    J[1][d] = -(B[0][0] * gr[1][d] - B[1][0] * gr[0][d]) / det;
+                    J[2][d] = -J[0][d] - J[1][d];
+                }
+                double tau[2];
+                for (int i = 0; i < 2; ++i) {
+                    double inv_D = 0.0;
+                    for (int j = 0; j < 3; ++j) {
+                        if (j == i) continue;
+                        double rho_ji = stoich_ratio_adv(p, Xn, i, j);
+                        if (p->ms_mode != 1) {
+                            double dot = 0.0, nn = 0.0;
+                            for (int d = 0; d < dims; ++d) {
+                                dot += J[j][d] * J[i][d];
+                                nn += J[i][d] * J[i][d];
+                            }
+                            const double e2 = p->eps * p->eps;
+                            rho_ji = (dot + e2 * rho_ji) / (nn + e2);
+                        }
+                        inv_D += (Xn[j] - Xn[i] * rho_ji) / p->Dl[i][j];
+                    }
+                    double t = 3.0 / inv_D + 0.5;
+                    if (!(t >= p->tau_min)) { t = p->tau_min; ++hits; }
+                    else if (t > p->tau_max) { t = p->tau_max; ++hits; }
+                    tau[i] = t;
+                }
+                if (tau_out) {
+                    tau_out[n] = tau[0];
+                    tau_out[N + n] = tau[1];
+                }
+                /* BGK toward Eq. 26, and the velocity model toward its Stokes equilibrium */
+                for (int a = 0; a < q; ++a) {
+                    const double eu = L->e[a][0] * u[0] + L->e[a][1] * u[1] + L->e[a][2] * u[2];
+                    const double em = L->e[a][0] * um[0] + L->e[a][1] * um[1] + L->e[a][2] * um[2];
+                    for (int s = 0; s < 2; ++s) {
+                        const long k = ((long)s * q + a) * N + n;
+                        const double feq = L->w[a] * Xn[s] * (1.0 + 3.0 * em);
+                        fstar[k] = f[k] - (f[k] - feq) / tau[s];
+                    }
+                    const long k = (long)a * N + n;
+                    const double geq = L->w[a] * (rho + 3.0 * eu);
+                    gstar[k] = g[k] - (g[k] - geq) / p->tau_flow;
+                }
+            }
+    free(X);
+    if (clamp_hits) *clamp_hits = hits;
+    return 0;
+}
+
+/* Streaming of the velocity model: the species rules with rho_in = 1 at the inlet and the total
+ * outflow Q_t per open outlet node. */
+static void stream_flow(const orc_params* p, const orc_lattice* L, const uint8_t* solid,
+                        const double* gstar, double* gnext)
+{
+    const long N = (long)p->nx * p->ny * p->nz;
+    const int q = L->q;
+    const double Qt = p->Q[0] + p->Q[1];
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                const long n = node_index(p, x, y, z);
+                if (solid[n]) {
+                    for (int a = 0; a < q; ++a) gnext[(long)a * N + n] = 0.0;
+                    continue;
+                }
+                int kind[ORC_QMAX];
+                for (int a = 0; a < q; ++a) {
+                    int sx = x - L->e[a][0];
+                    int sy = wrap(y - L->e[a][1], p->ny);
+                    int sz = wrap(z - L->e[a][2], p->nz);
+                    kind[a] = 0;
+                    if (sx < 0) { kind[a] = 1; continue; }
+                    if (sx >= p->nx) { kind[a] = 2; continue; }
+                    long src = node_index(p, sx, sy, sz);
+                    gnext[(long)a * N + n] = solid[src] ? gstar[(long)L->opp[a] * N + n]
+                                                        : gstar[(long)a * N + src];
+                }
+                for (int a = 0; a < q; ++a) {
+                    int b = L->opp[a];
+                    if (kind[a] == 1)
+                        gnext[(long)a * N + n] = (L->w[a] + L->w[b]) * 1.0 - gnext[(long)b * N + n];
+                    else if (kind[a] == 2)
+                        gnext[(long)a * N + n] = gstar[(long)b * N + n] - (L->w[b] / L->Wn) * Qt;
+                }
+            }
+}
+
+/* One step of the coupled pair: (f, g, u^{t-1}) -> (fnext, gnext, u^t). */
+int orc_step_adv(const orc_params* p, const uint8_t* solid, const double* f, const double* g,
+                 const double* uprev, double* fnext, double* gnext, double* ucur, orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long N = (long)p->nx * p->ny * p->nz;
+    double* fstar = (double*)malloc(sizeof(double) * 2 * L.q * N);
+    double* gstar = (double*)malloc(sizeof(double) * L.q * N);
+    if (!fstar || !gstar) {
+        free(fstar);
+        free(gstar);
+        return -8;
+    }
+    long hits = 0;
+    int rc = collide_adv(p, &L, solid, f, g, uprev, fstar, gstar, ucur, NULL, NULL, &hits);
+    if (rc == 0) {
+        orc_stats tmp;
+        memset(&tmp, 0, sizeof(tmp));
+        stream_all(p, &L, solid, fstar, fnext, &tmp);
+        stream_flow(p, &L, solid, gstar, gnext);
+        tmp.clamp_hits = hits;
+        if (st) *st = tmp;
+    }
+    free(fstar);
+    free(gstar);
+    return rc;
+}
+
+/* nsteps coupled steps in place on (f, g, uprev) (fwork, gwork: scratch of the sizes of f, g). */
+int orc_run_adv(const orc_params* p, const uint8_t* solid, double* f, double* g, double* uprev,
+                double* fwork, double* gwork, long nsteps, orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long N = (long)p->nx * p->ny * p->nz;
+    double* ucur = (double*)malloc(sizeof(double) * 3 * N);
+    if (!ucur) return -8;
+    long hits = 0;
+    for (long t = 0; t < nsteps; ++t) {
+        orc_stats s1;
+        int rc = orc_step_adv(p, solid, f, g, uprev, fwork, gwork, ucur, &s1);
+        if (rc) {
+            free(ucur);
+            return rc;
+        }
+        memcpy(f, fwork, sizeof(double) * 2 * L.q * N);
+        memcpy(g, gwork, sizeof(double) * L.q * N);
+        memcpy(uprev, ucur, sizeof(double) * 3 * N);
+        hits += s1.clamp_hits;
+        if (st) *st = s1;
+    }
+    free(ucur);
+    if (st) st->clamp_hits = hits;
+    return 0;
+}
+
+/* Post-collision state and diagnostics of the coupled pair: fstar, gstar, tau [2][N], and the
+ * velocity the species see, u_M [3][N]. */
+int orc_collide_adv(const orc_params* p, const uint8_t* solid, const double* f, const double* g,
+                    const double* uprev, double* fstar, double* gstar, double* tau_out,
+                    double* u_out, orc_stats* st)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    long hits = 0;
+    int rc = collide_adv(p, &L, solid, f, g, uprev, fstar, gstar, NULL, tau_out, u_out, &hits);
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->clamp_hits = hits;
+    }
+    return rc;
+}
+
+/* Velocity model at rest, g_a = w_a (rho = 1, u = 0), on fluid nodes. */
+void orc_flow_rest(const orc_params* p, const uint8_t* solid, double* g)
+{
+    orc_lattice L;
+    build_lattice(p->lattice, &L);
+    const long N = (long)p->nx * p->ny * p->nz;
+    for (int a = 0; a < L.q; ++a)
+        for (long n = 0; n < N; ++n) g[(long)a * N + n] = solid[n] ? 0.0 : L.w[a];
+}
+

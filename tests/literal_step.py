@@ -64,7 +64,8 @@ class LiteralStep:
     """Tiny-grid stepper.  mask: uint8 [nz, ny, nx] (1 = solid), used as given."""
 
     def __init__(self, case, mask, ms_mode_stoich: bool, eps: float,
-                 tau_min: float = 0.5 + 1e-9, tau_max: float = 1e6):
+                 tau_min: float = 0.5 + 1e-9, tau_max: float = 1e6, advection: bool = False,
+                 tau_flow: float = 1.0):
         self.nx, self.ny, self.nz = case.nx, case.ny, case.nz
         self.dims = 3 if case.lattice.startswith("D3") else 2
         e, w = VELOCITIES[case.lattice]
@@ -92,6 +93,8 @@ class LiteralStep:
         self.stoich = ms_mode_stoich
         self.eps = eps
         self.tau_min, self.tau_max = tau_min, tau_max
+        self.advection = advection
+        self.tau_flow = tau_flow
 
     def _n(self, x, y, z):
         return (z * self.ny + y) * self.nx + x
@@ -258,3 +261,130 @@ class LiteralStep:
     def to_array(self, f):
         """[2][Q][nz][ny][nx] numpy copy, velocity order of this module."""
         return np.array(f).reshape((2, self.q, self.nz, self.ny, self.nx))
+
+    # -- advective coupling (Eq. 26, second LB model for u_M) --------------------------------
+    #
+    # State (f, g, u_prev): species populations, the velocity model's populations (Stokes-limit
+    # equilibrium w_a (rho + 3 e_a . u), u = sum e_a g_a, BGK with tau_flow), and the velocity of
+    # the previous step.  The species relax toward w_a X (1 + 3 e_a . u_M) with u_M the mean
+    # velocity of this step and the last; Eq. 24 takes the diffusive fluxes J (Eq. 20), J_3 = -J_1
+    # - J_2, ratios J_j / J_i as projections regularized toward the 1D steady ratio
+    # (-nu_j - X_j Nt) / (-nu_i - X_i Nt), Nt = -(nu_1 + nu_2 + nu_3); Eq. 37's outlet gradient
+    # takes J_s = Q_s - X_s (Q_1 + Q_2).  The velocity model streams like a species whose inlet
+    # value is 1 and whose outlet flux is Q_1 + Q_2.
+
+    def flow_rest(self):
+        g = [[0.0] * self.N for _ in range(self.q)]
+        for n in range(self.N):
+            if not self.solid[n]:
+                for a in range(self.q):
+                    g[a][n] = self.w[a]
+        return g, [[0.0] * self.N for _ in range(3)]
+
+    def step_adv(self, f, g, uprev):
+        X = self.moments(f)
+        Qt = self.Q[0] + self.Q[1]
+        nt = -sum(self.nu)
+        fs = [[[0.0] * self.N for _ in range(self.q)] for _ in range(2)]
+        gs = [[0.0] * self.N for _ in range(self.q)]
+        ucur = [[0.0] * self.N for _ in range(3)]
+        for z in range(self.nz):
+            for y in range(self.ny):
+                for x in range(self.nx):
+                    n = self._n(x, y, z)
+                    if self.solid[n]:
+                        continue
+                    rho = sum(g[a][n] for a in range(self.q))
+                    u = [sum(self.e[a][d] * g[a][n] for a in range(self.q)) for d in range(3)]
+                    um = [(u[d] + uprev[d][n]) / 2.0 for d in range(3)]
+                    for d in range(3):
+                        ucur[d][n] = u[d]
+                    Xn = [X[0][n], X[1][n], X[2][n]]
+                    B = self._B(Xn)
+                    grad = [[0.0] * 3 for _ in range(2)]
+                    pos = [x, y, z]
+                    for d in range(self.dims):
+                        if d == 0 and x == self.nx - 1:
+                            Jb = [self.Q[0] - Xn[0] * Qt, self.Q[1] - Xn[1] * Qt]
+                            for s_ in range(2):
+                                grad[s_][0] = -(B[s_][0] * Jb[0] + B[s_][1] * Jb[1])
+                            continue
+                        up, dn = list(pos), list(pos)
+                        up[d] += 1
+                        dn[d] -= 1
+                        fu, fd = self._fluid(*up), self._fluid(*dn)
+                        for s_ in range(2):
+                            c = X[s_][n]
+                            vu = X[s_][self._n(up[0], up[1] % self.ny, up[2] % self.nz)] if fu else None
+                            vd = X[s_][self._n(dn[0], dn[1] % self.ny, dn[2] % self.nz)] if fd else None
+                            if fu and fd:
+                                grad[s_][d] = (vu - vd) / 2.0
+                            elif fu:
+                                grad[s_][d] = vu - c
+                            elif fd:
+                                grad[s_][d] = c - vd
+                    Bm = np.array(B)
+                    J = [[0.0] * 3 for _ in range(3)]
+                    for d in range(self.dims):
+                        sol = np.linalg.solve(Bm, np.array([grad[0][d], grad[1][d]]))
+                        J[0][d], J[1][d] = -float(sol[0]), -float(sol[1])
+                        J[2][d] = -J[0][d] - J[1][d]
+                    taus = [0.0, 0.0]
+                    for i in range(2):
+                        inv = 0.0
+                        for j in range(3):
+                            if j == i:
+                                continue
+                            r = (-self.nu[j] - Xn[j] * nt) / (-self.nu[i] - Xn[i] * nt)
+                            if not self.stoich:
+                                dot = sum(J[j][d] * J[i][d] for d in range(self.dims))
+                                nn = sum(J[i][d] * J[i][d] for d in range(self.dims))
+                                r = (dot + self.eps ** 2 * r) / (nn + self.eps ** 2)
+                            inv += (Xn[j] - Xn[i] * r) / self.Dl[i][j]
+                        taus[i] = min(max(3.0 / inv + 0.5, self.tau_min), self.tau_max)
+                    for a in range(self.q):
+                        em = sum(self.e[a][d] * um[d] for d in range(3))
+                        eu = sum(self.e[a][d] * u[d] for d in range(3))
+                        for s_ in range(2):
+                            feq = self.w[a] * Xn[s_] * (1.0 + 3.0 * em)
+                            fs[s_][a][n] = f[s_][a][n] - (f[s_][a][n] - feq) / taus[s_]
+                        geq = self.w[a] * (rho + 3.0 * eu)
+                        gs[a][n] = g[a][n] - (g[a][n] - geq) / self.tau_flow
+        fn = self._stream(fs, [self.X_in[0], self.X_in[1]], self.Q)
+        gn = self._stream([gs], [1.0], [Qt])[0]
+        return fn, gn, ucur
+
+    def _stream(self, fs, inlet, Q):
+        """Pull with bounce-back and the x-face rules for a list of fields."""
+        k = len(fs)
+        fn = [[[0.0] * self.N for _ in range(self.q)] for _ in range(k)]
+        for z in range(self.nz):
+            for y in range(self.ny):
+                for x in range(self.nx):
+                    n = self._n(x, y, z)
+                    if self.solid[n]:
+                        continue
+                    il, ol = [], []
+                    for a in range(self.q):
+                        sx, sy, sz = x - self.e[a][0], y - self.e[a][1], z - self.e[a][2]
+                        if sx < 0:
+                            il.append(a)
+                        elif sx >= self.nx:
+                            ol.append(a)
+                        elif self.solid[self._n(sx, sy % self.ny, sz % self.nz)]:
+                            for s_ in range(k):
+                                fn[s_][a][n] = fs[s_][self.opp[a]][n]
+                        else:
+                            m = self._n(sx, sy % self.ny, sz % self.nz)
+                            for s_ in range(k):
+                                fn[s_][a][n] = fs[s_][a][m]
+                    for a in il:
+                        b = self.opp[a]
+                        for s_ in range(k):
+                            fn[s_][a][n] = (self.w[a] + self.w[b]) * inlet[s_] - fn[s_][b][n]
+                    for a in ol:
+                        b = self.opp[a]
+                        for s_ in range(k):
+                            fn[s_][a][n] = fs[s_][b][n] - (self.w[b] / self.Wn) * Q[s_]
+        return fn
+
