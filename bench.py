@@ -1,21 +1,26 @@
 """Benchmark of the LBM / Maxwell-Stefan hot path on one MI355X.
 
-Workload (default): the 1024 x 1024 porous anode slice (overlapping disks, void fraction 0.40,
-seed 2), D2Q9, FP32 populations (FP64 Maxwell-Stefan solve and reductions), ternary
-H2-H2O-Ar, X_in ~ Dirichlet(6, 3, 1), j = 1 A/cm^2.  A step is one time step of the whole path
-(stream, boundaries, moments, gradients, Maxwell-Stefan solve, relaxation time, collision) over
-the slice; the residual reduction runs every --check-every steps inside the timed region and the
-overpotential once at its end, as in a steady solve.
+Workload (default): the batch of 64 ragged porous anode slices (D2Q9, sides 256..1024, void
+fraction U[0.3, 0.5], overlapping disks r ~ U[3, 12], one inlet composition, current densities
+U[0, 2] A/cm^2): 10.1 M fluid nodes, a 1.5 GB double-buffered FP32 state that does not fit the
+256 MB last-level cache, so the step kernel's rate is an HBM rate.  A step is one time step of the
+whole path (stream, boundaries, moments, gradients, Maxwell-Stefan solve, relaxation time,
+collision) over every instance, one kernel launch; hipGraph chunks of --check-every steps with
+the per-instance residual check between them, and the overpotential of every instance at the end.
+--workload porous_2d (the 1024^2 slice, 56 MB: cache-resident) and porous_3d (the 256^3 block)
+select the single-domain workloads.
 
 Prints one JSON line: species-MLUPS (fluid nodes x 2 evolved species x steps / s / 1e6) as the
 value, the step kernel's roofline (algorithmic bytes per launch over its mean duration from HIP
 events on the launch stream), and the FP64 CPU oracle's rate on a bounded sample of the same
-workload.
+workload, taken before the GPU is touched: for the batch one worker process per host core (up
+to 16), each stepping its own instance; for a single domain one thread.
 """
 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -68,10 +73,28 @@ def measured_traffic(workload_key: str, kernel: str):
         return None
 
 
-def cpu_baseline(case, steps: int):
-    """The FP64 CPU oracle as it stands, timed on a bounded sample of the same workload: `steps`
-    steps of the whole slice (2D), or of the block's first 32 z-planes stepped as a periodic slab
-    (3D: the whole 256^3 block takes the oracle about a minute per step and 15 GB of memory)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _oracle_sample(case, steps: int):
+    """Oracle steps on one problem (or the first 32 z-planes of a 3D block as a periodic slab);
+    returns (fluid nodes, steps, seconds)."""
     import dataclasses
     import numpy as np
     import oracle
@@ -83,16 +106,71 @@ def cpu_baseline(case, steps: int):
     o.step(1)  # warm-up (allocations, page faults)
     t0 = time.perf_counter()
     o.step(steps)
-    dt = time.perf_counter() - t0
-    n_fluid = int(o.fluid().sum())
-    if sample is case:
-        what = "the same %s slice" % "x".join(str(v) for v in (case.nx, case.ny, case.nz)[:2 if case.nz == 1 else 3])
+    return int(o.fluid().sum()), steps, time.perf_counter() - t0
+
+
+def _oracle_timed(case, seconds: float):
+    """Oracle steps on one problem in chunks until `seconds` have passed: (fluid, steps, s)."""
+    import oracle
+    o = oracle.Oracle(case)
+    o.init_uniform()
+    o.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(5)
+        steps += 5
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return int(o.fluid().sum()), steps, dt
+
+
+def cpu_baseline(case, steps: int):
+    """The FP64 CPU oracle as it stands, single thread, on a bounded sample of the workload:
+    `steps` steps of the whole slice (2D), or of the block's first 32 z-planes stepped as a
+    periodic slab (3D: the whole 256^3 block takes the oracle about a minute per step and 15 GB
+    of memory)."""
+    n_fluid, steps, dt = _oracle_sample(case, steps)
+    if case.nz == 1:
+        what = "the same %dx%d slice" % (case.nx, case.ny)
     else:
-        what = "the first %d z-planes of the same %dx%dx%d block as a periodic slab" % (
-            sample.nz, case.nx, case.ny, case.nz)
+        what = "the first 32 z-planes of the same %dx%dx%d block as a periodic slab" % (
+            case.nx, case.ny, case.nz)
     return {"value": 2.0 * n_fluid * steps / dt / 1e6, "unit": "species-MLUPS", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": "%d steps of %s (%d fluid nodes), FP64, single thread" % (steps, what, n_fluid)}
+
+
+def cpu_baseline_batch(cases, seconds: float = 12.0):
+    """The oracle on the batch: one worker process per host core (at most 16, the host share of
+    one GPU), each stepping its own instance of the batch for `seconds`; the instances are
+    independent, so the aggregate is the oracle's batch throughput on this host.  The workers
+    are fresh interpreters (spawned, not forked: a forked copy of a process that has loaded the
+    GPU runtime must not touch it), started before this process initializes the GPU."""
+    import multiprocessing as mp
+    P = _host_cores()
+    order = sorted(range(len(cases)), key=lambda k: cases[k].nx)
+    pick = [cases[order[(i * len(order)) // P]] for i in range(P)]  # spread over the sizes
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(P) as pool:
+        res = pool.starmap(_oracle_timed, [(c, seconds) for c in pick])
+    agg = sum(2.0 * nf * st / dt for nf, st, dt in res) / 1e6
+    return {"value": agg, "unit": "species-MLUPS", "cores": P, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "per_worker_mean": agg / P,
+            "sample": "%d concurrent oracle processes, one per core, each stepping one instance "
+                      "of the batch (sides %s) for about %.0f s, FP64" % (
+                          P, ",".join(str(c.nx) for c in pick), seconds)}
+
+
+def storage_label(precision: str, shift: str) -> str:
+    """FP64 and FP32 global storage hold f itself; 16-bit global storage holds f - w_a X_in; the
+    NODE shift holds f - w_a c(r) with an FP64 reference per node."""
+    if shift == "node":
+        return precision + "-node-shift"
+    if precision in ("fp16", "bf16"):
+        return precision + "-global-shift"
+    return precision
 
 
 def main(argv=None):
@@ -102,7 +180,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--shift", default="global", choices=["global", "node"])
-    ap.add_argument("--workload", default="porous_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
+    ap.add_argument("--workload", default="batch_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
     ap.add_argument("--lattice", default="", choices=["", "d2q9", "d2q5", "d3q19", "d3q7"],
                     help="velocity set: d2q9 (default) or d2q5 for porous_2d, d3q19 (default) or "
                          "d3q7 for porous_3d")
@@ -110,7 +188,9 @@ def main(argv=None):
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--chunk-z", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=0,
-                    help="oracle steps of the CPU baseline (default 40 in 2D, 6 in 3D)")
+                    help="oracle steps of the single-domain CPU baseline (default 40 in 2D, 6 in 3D)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="seconds each oracle worker steps in the batch CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
     lattices = WORKLOAD_LATTICES[args.workload]
@@ -123,13 +203,20 @@ def main(argv=None):
               "(use --gpus 1)", file=sys.stderr)
         return 2
 
-    import torch
     from paper_1809_01600_amd import inputs, lbm_ms
 
+    if args.workload == "batch_2d":
+        cases = inputs.batch_2d(tau_ref=3.0,
+                                accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+        # the oracle leg first: its worker processes start before the GPU is initialized
+        cpu = None if args.no_cpu else cpu_baseline_batch(cases, args.cpu_seconds)
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        return run_batch(args, cases, cpu)
+    import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload == "batch_2d":
-        return run_batch(args)
     if args.workload == "porous_2d":
         case = inputs.porous_2d()
         case.lattice = args.lattice
@@ -147,20 +234,27 @@ def main(argv=None):
     n_fluid = int(info.n_fluid)
     s.init()
     s.step(args.warmup)
-    s.residual()
+    check = lambda: lbm_ms.lib().lbm_ms_residual(s.h, ctypes.byref(res))  # noqa: E731
+    res = ctypes.c_double(0.0)
+    check()
     torch.cuda.synchronize()
 
-    # timed region: K steps with the residual check every check_every steps, then eta
+    # timed region: K steps with the residual check every check_every steps, then eta.  A check
+    # that finds a negative fraction (the limiting current reached in a dead-end pore) or a
+    # clamp is recorded, not fatal: this measures the step's throughput.
     K = args.steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
+    statuses = set()
     while done < K:
         n = min(args.check_every, K - done)
         s.step(n)
         done += n
-        r = s.residual()
-    eta = s.overpotential()
+        statuses.add(int(check()))
+    r = res.value
+    eta_rc = lbm_ms.lib().lbm_ms_overpotential(s.h, ctypes.byref(res))
+    eta = res.value if eta_rc == 0 else None
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -194,7 +288,7 @@ def main(argv=None):
             "lattice": case.lattice,
             "nx": case.nx, "ny": case.ny, "nz": case.nz,
             "fluid_nodes": n_fluid,
-            "storage": args.precision + ("" if args.precision == "fp64" else "-" + args.shift + "-shift"),
+            "storage": storage_label(args.precision, args.shift),
             "ms_solve": "fp64",
             "tau_ref": case.tau_ref,
             "check_every": args.check_every,
@@ -202,6 +296,7 @@ def main(argv=None):
             "node_mlups": round(n_fluid * K / elapsed / 1e6, 1),
             "residual_at_end": r,
             "eta_V": eta,
+            "check_status": sorted(statuses),
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -223,14 +318,12 @@ def main(argv=None):
     return 0
 
 
-def run_batch(args):
+def run_batch(args, cases, cpu):
     """64 ragged porous slices (sides 256..1024, one inlet composition, j ~ U[0, 2] A/cm^2) in one
     launch per step, hipGraph chunks of --check-every steps with the per-instance residual check
     between them, autotuned tile height."""
     import torch
-    from paper_1809_01600_amd import autotune, inputs, lbm_ms
-    cases = inputs.batch_2d(tau_ref=3.0,
-                            accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+    from paper_1809_01600_amd import autotune, lbm_ms
     shift = lbm_ms.SHIFT_NODE if args.shift == "node" else lbm_ms.SHIFT_GLOBAL
     b = lbm_ms.Batch(cases, precision=args.precision, shift_mode=shift)
     tile = autotune.tune_batch(b)
@@ -276,7 +369,7 @@ def run_batch(args):
             "instances": len(cases),
             "fluid_nodes": int(n_fluid),
             "tiles": int(n_tiles),
-            "storage": args.precision + ("" if args.precision == "fp64" else "-" + args.shift + "-shift"),
+            "storage": storage_label(args.precision, args.shift),
             "ms_solve": "fp64",
             "check_every": args.check_every,
             "graphs": True,
@@ -299,9 +392,8 @@ def run_batch(args):
             "bytes_per_launch": bytes_per_launch,
         },
     }
-    if not args.no_cpu:
-        small = min(range(len(cases)), key=lambda k: cases[k].nx)
-        line["cpu_baseline"] = cpu_baseline(cases[small], args.cpu_steps or 40)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     b.close()
     return 0
