@@ -83,7 +83,9 @@ typedef struct {
     double p;             /* Pa; C_t = p / (R T), R = 8.3145 */
     double D[9];          /* binary Maxwell-Stefan diffusivities D_ij [m^2/s], row-major 3x3,
                              symmetric, diagonal ignored */
-    int nu[3];            /* stoichiometric coefficients (Eq. 39); need nu1 = -nu2 != 0, nu3 = 0 */
+    int nu[3];            /* stoichiometric coefficients (Eq. 39); need nu1 = -nu2 != 0, nu3 = 0,
+                             or with advection nu1 != 0, nu2 != 0, nu3 = 0 and the 1D flux ratios
+                             finite: -nu_s and -nu_s + nu1 + nu2 nonzero and of one sign, s = 1, 2 */
     int n_electrons;      /* electrons per reaction (Eq. 39, Eq. 43) */
     double dx;            /* lattice spacing [m] */
     double tau_ref;       /* dt = (tau_ref - 1/2) dx^2 / (3 max D_ij): the fastest binary pair
@@ -103,6 +105,21 @@ typedef struct {
     void* stream;         /* hipStream_t */
     int collision;        /* LBM_MS_BGK (0, the paper's) or LBM_MS_TRT */
     double trt_lambda;    /* TRT Lambda = (tau_even - 1/2)(tau - 1/2); <= 0 selects 1/4 */
+    int advection;        /* 1: advective coupling (Sec. 3.1, Eq. 20-21 and 26) for reactions that
+                             change the number of moles, nu1 + nu2 != 0: the species equilibrium
+                             carries the molar-averaged velocity u_M = N_t / C_t of a second
+                             lattice Boltzmann model (Stokes limit of an incompressible model with
+                             the total concentration as density; no-slip on solid, inlet at the
+                             channel's concentration, the electrode's total molar flux at each open
+                             outlet node), the species see the mean u_M of the current and the
+                             previous step, and Eq. 24 takes the diffusive fluxes J_s = N_s - X_s N_t
+                             (Eq. 20) with J_j / J_i read as the projection of the vectors,
+                             regularized toward the 1D steady ratio (-nu_j - X_j Nt) / (-nu_i - X_i
+                             Nt), Nt = -(nu1 + nu2), which is also the STOICH variant.  Single
+                             instances with FP64 or FP32 global storage, BGK, Dirichlet inlet, no
+                             volumetric source and no checkpoints (E_ARG / E_STATE otherwise).
+                             0: the equimolar method (Eq. 29), which needs nu1 = -nu2. */
+    double tau_flow;      /* relaxation time of the velocity model (> 1/2; <= 0 selects 1) */
 } lbm_ms_params;
 
 typedef struct {
@@ -211,6 +228,12 @@ int lbm_ms_overpotential(lbm_ms_t h, double* eta_volts);
 /* Mole-fraction field of the current state.  X: [3][N] float64 in host memory (on_device = 0)
  * or device memory (on_device = 1); solid nodes read 0. */
 int lbm_ms_get_fields(lbm_ms_t h, double* X, int on_device);
+
+/* Advective coupling only: the molar-averaged velocity u_M that the species see (the mean of the
+ * velocity model's node velocity over the current and the previous step), in m/s, as [3][N]
+ * float64 in host memory (solid voxels 0; the third component is 0 in 2D).  E_STATE without
+ * advection. */
+int lbm_ms_get_velocity(lbm_ms_t h, double* u_host);
 
 /* Post-collision populations of the current state, decoded to float64, host [2][Q][N], in the
  * velocity order of lbm_ms_lattice_info. */

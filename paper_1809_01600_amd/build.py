@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm_ms.so")
-SOURCES = ["lbm_ms_kernels.hip", "lbm_ms_runtime.hip", "lbm_cnn_kernels.hip"]
+SOURCES = ["lbm_ms_kernels.hip", "lbm_ms_advect.hip", "lbm_ms_runtime.hip", "lbm_cnn_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

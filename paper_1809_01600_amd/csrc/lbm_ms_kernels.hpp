@@ -29,4 +29,27 @@ hipError_t launch_populations(hipStream_t st, const StepArgs& a, int lattice, in
 hipError_t launch_paper_profile(hipStream_t st, const StepArgs& a, double Qs0, double Qs1,
                                 double* prof, double* X);
 
+// Advective coupling (lbm_ms_advect.hip): the velocity model's buffers and constants of one step.
+struct AdvArgs {
+    const void* gin;    // velocity model, post-collision populations of the previous step [Q][P]
+    void* gout;         // ... of this step
+    const double* xc;   // X of this step per compact node [2][NF] (written by the first pass)
+    const double* uin;  // node velocity of the previous step [3][NF]
+    double* uout;       // node velocity of this step [3][NF]
+    double Qt;          // total lattice outflow per open outlet node, Q_1 + Q_2
+    double om_flow;     // 1 / tau_flow
+    double nh0, nh1, nh2, nht;  // -nu_s and their sum: the direction of the electrode fluxes
+    double eps2;        // square of the flux regularizer
+};
+// one coupled step: X pass into xw (= v.xc), then the step; FP64 or FP32 storage, every lattice
+hipError_t launch_adv_step(hipStream_t st, const StepArgs& a, const AdvArgs& v, double* xw,
+                           int lattice, int prec);
+// velocity model at rest into v.gout, zero node velocities in v.uout and u_other
+hipError_t launch_adv_rest(hipStream_t st, const StepArgs& a, const AdvArgs& v, double* u_other,
+                           int lattice, int prec);
+// u_M = (ucur + uprev) / 2 times scale into out[3][N] (solid voxels 0)
+hipError_t launch_adv_velocity(hipStream_t st, const StepArgs& a, const double* ucur,
+                               const double* uprev, double scale, double* out, int lattice,
+                               int prec);
+
 }  // namespace lbmms

@@ -28,6 +28,7 @@ constexpr uint64_t STATE_MAGIC = 0x314d534c42304c31ull;
 struct Layout {
     size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
     size_t tile_cap, ent_cap;
+    size_t g[2], u[2], xa;  // advective coupling: velocity model, node velocities, X per node
 };
 
 int q_of(int lattice)
@@ -88,8 +89,28 @@ bool valid_params(const lbm_ms_params* p, std::string* why)
     const double d12 = p->D[1], d13 = p->D[2], d23 = p->D[5];
     if (!(d12 > 0) || !(d13 > 0) || !(d23 > 0)) return fail("binary diffusivities must be positive");
     if (p->D[3] != d12 || p->D[6] != d13 || p->D[7] != d23) return fail("D must be symmetric");
-    if (p->nu[2] != 0 || p->nu[0] == 0 || p->nu[0] != -p->nu[1])
-        return fail("need nu1 = -nu2 != 0 and nu3 = 0 (equimolar counter-diffusion)");
+    if (p->advection != 0 && p->advection != 1) return fail("advection must be 0 or 1");
+    if (!p->advection) {
+        if (p->nu[2] != 0 || p->nu[0] == 0 || p->nu[0] != -p->nu[1])
+            return fail("need nu1 = -nu2 != 0 and nu3 = 0 (equimolar counter-diffusion); a "
+                        "reaction that changes the number of moles needs advection = 1");
+    } else {
+        if (p->nu[2] != 0 || p->nu[0] == 0 || p->nu[1] == 0)
+            return fail("advection: need nu1 != 0, nu2 != 0, nu3 = 0");
+        // the 1D steady flux ratios (-nu_j - X_j Nt) / (-nu_i - X_i Nt) must stay finite for
+        // X in [0, 1]: -nu_i and -nu_i - Nt nonzero and of one sign
+        const double nt = -(double)(p->nu[0] + p->nu[1]);
+        for (int i = 0; i < 2; ++i) {
+            const double a0 = -(double)p->nu[i], a1 = a0 - nt;
+            if (!(a0 * a1 > 0)) return fail("advection: these nu make a 1D flux ratio vanish");
+        }
+        if (p->precision != LBM_MS_FP64 && p->precision != LBM_MS_FP32)
+            return fail("advection: FP64 or FP32 storage");
+        if (p->shift_mode != LBM_MS_SHIFT_GLOBAL) return fail("advection: global storage only");
+        if (p->collision != LBM_MS_BGK) return fail("advection: BGK collision only");
+        if (p->inlet_mode != LBM_MS_INLET_DIRICHLET) return fail("advection: Dirichlet inlet only");
+        if (!(p->tau_flow <= 0 || p->tau_flow > 0.5)) return fail("advection: tau_flow must exceed 1/2");
+    }
     if (p->n_electrons <= 0) return fail("n_electrons must be positive");
     return true;
 }
@@ -130,6 +151,14 @@ Layout layout(const lbm_ms_params& p)
     L.inst = take(2 * sizeof(StepArgs));
     L.tiles = take(L.tile_cap * 2 * sizeof(int4));
     L.ent = take(L.ent_cap * sizeof(uint32_t));
+    if (p.advection) {
+        const size_t gb = (size_t)q * (size_t)plane_pitch((long long)N) * elem_bytes(p.precision);
+        L.g[0] = take(gb);
+        L.g[1] = take(gb);
+        L.u[0] = take(3ull * N * sizeof(double));
+        L.u[1] = take(3ull * N * sizeof(double));
+        L.xa = take(2ull * N * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -226,6 +255,24 @@ struct lbm_ms_s {
         a.trt = p.collision == LBM_MS_TRT ? 1 : 0;
         a.trt_lambda = p.trt_lambda > 0 ? p.trt_lambda : 0.25;
         return a;
+    }
+    // advective coupling: the velocity model's buffers of a step that reads parity in_buf
+    AdvArgs adv_args(int in_buf) const
+    {
+        AdvArgs v{};
+        v.gin = ws + L.g[in_buf];
+        v.gout = ws + L.g[1 - in_buf];
+        v.xc = reinterpret_cast<const double*>(ws + L.xa);
+        v.uin = reinterpret_cast<const double*>(ws + L.u[in_buf]);
+        v.uout = reinterpret_cast<double*>(ws + L.u[1 - in_buf]);
+        v.Qt = Q[0] + Q[1];
+        v.om_flow = 1.0 / (p.tau_flow > 0 ? p.tau_flow : 1.0);
+        v.nh0 = -(double)p.nu[0];
+        v.nh1 = -(double)p.nu[1];
+        v.nh2 = -(double)p.nu[2];
+        v.nht = v.nh0 + v.nh1 + v.nh2;
+        v.eps2 = eps * eps;
+        return v;
     }
     int nblocks_step() const
     {
@@ -811,6 +858,7 @@ int lbm_ms_set_source(lbm_ms_t h, int x_first, double j)
 {
     if (!h) return LBM_MS_E_ARG;
     if (!h->geom) return h->fail(LBM_MS_E_STATE, "set_geometry first");
+    if (h->p.advection) return h->fail(LBM_MS_E_ARG, "no volumetric source with advection");
     if (x_first < 0 || x_first > h->p.nx) return h->fail(LBM_MS_E_ARG, "x_first must lie in [0, nx]");
     if (!(j >= 0.0) || !std::isfinite(j)) return h->fail(LBM_MS_E_ARG, "j must be finite and >= 0");
     long long n = 0;
@@ -836,6 +884,12 @@ static int init_common(lbm_ms_t h, const double* Xdev)
     int rc = h->hip(launch_init(h->stream, a, h->p.lattice, h->prec(), h->ns(), Xdev, h->Xin[0],
                                 h->Xin[1]), "init kernel");
     if (rc) return rc;
+    if (h->p.advection) {  // velocity model at rest, zero velocities of both parities
+        rc = h->hip(launch_adv_rest(h->stream, a, h->adv_args(1),
+                                    reinterpret_cast<double*>(h->at(h->L.u[1])), h->p.lattice,
+                                    h->prec()), "velocity model init");
+        if (rc) return rc;
+    }
     rc = h->hip(hipMemsetAsync(h->at(h->L.flags), 0, 64, h->stream), "flag reset");
     if (rc) return rc;
     // residual snapshot of the initial state
@@ -907,7 +961,10 @@ int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
     const unsigned* ent = reinterpret_cast<const unsigned*>(h->ws + h->L.ent);
     for (int64_t t = 0; t < nsteps; ++t) {
         hipError_t e;
-        if (is_2d(h->p.lattice)) {
+        if (h->p.advection) {
+            e = launch_adv_step(h->stream, h->args(h->cur), h->adv_args(h->cur),
+                                reinterpret_cast<double*>(h->at(h->L.xa)), h->p.lattice, h->prec());
+        } else if (is_2d(h->p.lattice)) {
             e = launch_step2d(h->stream, tab + h->cur, tiles, ent, h->ntiles, h->p.lattice, h->prec(),
                               h->ns(), h->ty, h->cz);
         } else {
@@ -1089,6 +1146,26 @@ int lbm_ms_get_fields(lbm_ms_t h, double* X, int on_device)
     return h->sync();
 }
 
+int lbm_ms_get_velocity(lbm_ms_t h, double* u)
+{
+    if (!h || !u) return LBM_MS_E_ARG;
+    if (!h->p.advection) return h->fail(LBM_MS_E_STATE, "no velocity model without advection");
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    // after a step of parity c the buffer u[1 - c] holds this step's node velocity, u[c] the
+    // previous one; with h->cur already flipped, u[cur] is the latest
+    StepArgs a = h->args(h->cur);
+    double* dst = (double*)h->at(h->L.field);
+    const double scale = h->p.dx / h->dt;  // lattice velocity to m/s
+    int rc = h->hip(launch_adv_velocity(h->stream, a, (const double*)h->at(h->L.u[h->cur]),
+                                        (const double*)h->at(h->L.u[1 - h->cur]), scale, dst,
+                                        h->p.lattice, h->prec()), "velocity");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(u, dst, 3ull * h->N * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                "velocity readback");
+    if (rc) return rc;
+    return h->sync();
+}
+
 int lbm_ms_get_populations(lbm_ms_t h, double* f)
 {
     if (!h || !f) return LBM_MS_E_ARG;
@@ -1119,6 +1196,7 @@ struct StateHeader {
 int lbm_ms_save_state(lbm_ms_t h, void* buf, size_t* bytes)
 {
     if (!h || !bytes) return LBM_MS_E_ARG;
+    if (h->p.advection) return h->fail(LBM_MS_E_STATE, "no checkpoints with advection");
     const size_t fb = 2ull * h->q * h->P * elem_bytes(h->p.precision);
     const size_t xb = node_shift(h->p) ? 2ull * h->n_fluid * sizeof(double) : 0;
     const size_t sb = 2ull * h->n_fluid * sizeof(double);
@@ -1147,6 +1225,7 @@ int lbm_ms_save_state(lbm_ms_t h, void* buf, size_t* bytes)
 int lbm_ms_load_state(lbm_ms_t h, const void* buf, size_t bytes)
 {
     if (!h || !buf) return LBM_MS_E_ARG;
+    if (h->p.advection) return h->fail(LBM_MS_E_STATE, "no checkpoints with advection");
     if (!h->geom || !h->bc) return h->fail(LBM_MS_E_STATE, "set_geometry and set_bc first");
     StateHeader H;
     if (bytes < sizeof(H)) return h->fail(LBM_MS_E_ARG, "blob too small");
@@ -1376,7 +1455,8 @@ bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
                   std::vector<size_t>* offs, size_t* off_tab, size_t* off_tiles, size_t* off_ent,
                   size_t* tile_cap, size_t* ent_cap, size_t* total)
 {
-    if (!common || !inst || count <= 0 || !is_2d(common->lattice)) return false;
+    // batches step through the tile work list, which has no advective coupling
+    if (!common || !inst || count <= 0 || !is_2d(common->lattice) || common->advection) return false;
     size_t off = 0, tc = 0, ec = 0;
     auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
     if (offs) offs->clear();
@@ -1439,8 +1519,9 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     std::vector<size_t> offs;
     size_t ot, oti, oe, tc, ec, total;
     if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &tc, &ec, &total))
-        return create_fail(LBM_MS_E_ARG, "invalid batch parameters (D2Q9 common parameters, "
-                                         "count > 0, every instance valid with a solid mask)");
+        return create_fail(LBM_MS_E_ARG, "invalid batch parameters (2D common parameters without "
+                                         "advection, count > 0, every instance valid with a solid "
+                                         "mask)");
     if (!d_workspace || ((uintptr_t)d_workspace & 255))
         return create_fail(LBM_MS_E_ARG, "workspace is NULL or not 256-byte aligned");
     if (bytes < total)

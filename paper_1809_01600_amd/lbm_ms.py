@@ -55,6 +55,8 @@ class lbm_ms_params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("collision", ctypes.c_int),
         ("trt_lambda", ctypes.c_double),
+        ("advection", ctypes.c_int),
+        ("tau_flow", ctypes.c_double),
     ]
 
 
@@ -125,6 +127,7 @@ _SIGNATURES = [
     ("lbm_ms_overpotential", ctypes.c_int, [_VP, _DP]),
     ("lbm_ms_get_fields", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_ms_get_populations", ctypes.c_int, [_VP, _DP]),
+    ("lbm_ms_get_velocity", ctypes.c_int, [_VP, _DP]),
     ("lbm_ms_mass_balance", ctypes.c_int, [_VP, _DP, _DP, _DP]),
     ("lbm_ms_save_state", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_size_t)]),
     ("lbm_ms_load_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
@@ -171,6 +174,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblbm_ms.so is not built (run __graft_entry__.build() or "
                               "python paper_1809_01600_amd/build.py)")
+        # torch first: the library links libamdhip64.so.7, and torch carries its own copy under
+        # that soname; loaded first, torch's copy satisfies the library too.  Loaded the other
+        # way round, the process would map two HIP runtimes, and streams or memory of one would
+        # be invalid in the other.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGNATURES:
             fn = getattr(L, name)
@@ -240,7 +248,8 @@ def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
                 ms_mode: int = LOCAL_FLUX, inlet_mode: int = INLET_DIRICHLET,
                 eps_flux: float = -1.0, tau_min: float = 0.0, tau_max: float = 0.0,
                 tile_y: int = 0, chunk_z: int = 0, stream: Optional[int] = None,
-                collision="bgk", trt_lambda: float = 0.0) -> lbm_ms_params:
+                collision="bgk", trt_lambda: float = 0.0, advection: bool = False,
+                tau_flow: float = 0.0) -> lbm_ms_params:
     """Marshal a physical problem description (inputs.Case) into lbm_ms_params."""
     p = lbm_ms_params()
     p.lattice = LATTICES[case.lattice]
@@ -264,6 +273,8 @@ def make_params(case, precision: int = FP64, shift_mode: int = SHIFT_GLOBAL,
     p.stream = stream
     p.collision = COLLISIONS[collision] if isinstance(collision, str) else int(collision)
     p.trt_lambda = trt_lambda
+    p.advection = 1 if advection else 0
+    p.tau_flow = tau_flow
     return p
 
 
@@ -273,7 +284,7 @@ class Solver:
     def __init__(self, case, precision="fp64", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
                  inlet_mode=INLET_DIRICHLET, eps_flux=-1.0, tau_min=0.0, tau_max=0.0,
                  tile_y=0, chunk_z=0, device="cuda", set_geometry=True, set_bc=True,
-                 collision="bgk", trt_lambda=0.0):
+                 collision="bgk", trt_lambda=0.0, advection=False, tau_flow=0.0):
         import torch
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -282,7 +293,7 @@ class Solver:
         self.stream = torch.cuda.current_stream(self.torch_device)
         self.params = make_params(case, precision, shift_mode, ms_mode, inlet_mode, eps_flux,
                                   tau_min, tau_max, tile_y, chunk_z, self.stream.cuda_stream,
-                                  collision, trt_lambda)
+                                  collision, trt_lambda, advection, tau_flow)
         nbytes = lib().lbm_ms_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise LbmMsError(E_ARG, lib().lbm_ms_last_error(None).decode())
@@ -408,6 +419,12 @@ class Solver:
         self._check(lib().lbm_ms_get_fields(self.h, X.ctypes.data_as(_VP), 0))
         return X.reshape((3,) + self.case.shape)
 
+    def get_velocity(self) -> np.ndarray:
+        """Advective coupling: u_M [3, nz, ny, nx] in m/s (the velocity the species see)."""
+        u = np.empty(3 * self.N)
+        self._check(lib().lbm_ms_get_velocity(self.h, _dp(u)))
+        return u.reshape((3,) + self.case.shape)
+
     def get_populations(self) -> np.ndarray:
         f = np.empty(2 * self.q * self.N)
         self._check(lib().lbm_ms_get_populations(self.h, _dp(f)))
@@ -457,7 +474,8 @@ class Batch:
     lbm_ms.h)."""
 
     def __init__(self, cases, precision="fp32", shift_mode=SHIFT_GLOBAL, ms_mode=LOCAL_FLUX,
-                 tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0, rows=0):
+                 tile_y=0, eps_flux=-1.0, device="cuda", collision="bgk", trt_lambda=0.0, rows=0,
+                 advection=False):
         import torch
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -472,7 +490,8 @@ class Batch:
             raise ValueError("batched solves are two-dimensional (D2Q9 or D2Q5)")
         self.stream = torch.cuda.current_stream(torch.device(device))
         self.params = make_params(c0, precision, shift_mode, ms_mode, INLET_DIRICHLET, eps_flux,
-                                  0.0, 0.0, tile_y, rows, self.stream.cuda_stream, collision, trt_lambda)
+                                  0.0, 0.0, tile_y, rows, self.stream.cuda_stream, collision, trt_lambda,
+                                  advection)
         n = len(self.cases)
         self._masks = [np.ascontiguousarray(c.mask(), dtype=np.uint8).reshape(-1) for c in self.cases]
         self.desc = (lbm_ms_instance_desc * n)()
