@@ -57,12 +57,22 @@ def test_backward_matches_reference():
         assert np.max(np.abs(gb - rgb)) <= 1e-4 * max(np.max(np.abs(rgb)), 1e-12), li
 
 
-def test_bf16_inference_close_to_fp32():
+def test_bf16_inference_against_the_fp64_reference():
+    """BF16 activations and weights with FP32 accumulation, against the FP64 reference forward.
+    Each layer rounds its inputs and weights to 8 significant bits (relative 2^-9 each) and sums
+    up to 288 products of random sign, so a layer's output carries about 2^-9 sqrt(2) = 2.8e-3 of
+    its typical magnitude, plus 2^-9 for its own rounding; over five layers that is about 1e-2,
+    and the bound allows twice that."""
     net, feat, _, _ = _net_and_data(B=1, H=40, W=70, seed=5)
     ft = torch.tensor(feat, device="cuda")
-    p32 = net.forward(ft)[-1].cpu().numpy()
-    p16 = net.predict_bf16(ft).cpu().numpy()
-    assert np.max(np.abs(p16 - p32)) <= 0.05 * max(1.0, np.max(np.abs(p32)))
+    p16 = net.predict_bf16(ft).cpu().double().numpy()
+    r = ref.forward(_layers(net), feat.astype(np.float64))[-1]
+    err = np.max(np.abs(p16 - r)) / np.max(np.abs(r))
+    print("BF16 inference vs FP64 reference: max error %.2e of max |output|" % err)
+    assert err <= 2e-2
+    # and the FP32 forward is far closer
+    p32 = net.forward(ft)[-1].cpu().double().numpy()
+    assert np.max(np.abs(p32 - r)) <= 2e-5 * np.max(np.abs(r))
 
 
 def test_training_reduces_loss():

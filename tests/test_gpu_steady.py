@@ -135,7 +135,7 @@ def test_node_shift_steady_states_of_the_precision_study(precision):
     mole fraction and 1e-6 V in eta."""
     from paper_1809_01600_amd import warmstart
     print("precision study", precision, flush=True)
-    res = warmstart.precision_study(n=8, side=128, tol=1e-10, max_steps=1_500_000,
+    res = warmstart.precision_study(n=8, side=128, tol=1e-10, max_steps=3_000_000,
                                     modes=[precision + "_node"], log=lambda m: print(m, flush=True))
     rec = res[precision + "_node"]
     assert all(st == 0 for st in rec["status"]), rec["status"]
