@@ -53,6 +53,17 @@ __device__ inline void halo_pos(int t, int& hx, int& hy)
     else { hx = 0; hy = 0; }
 }
 
+// Periodic row of the staged region: gy = y0 - 2 + ry lies in [-2, ny + RY - 3] for a tile
+// origin y0 in [0, ny), so one conditional wrap suffices once ny >= RY; smaller boxes (a
+// workgroup-uniform branch) take the general remainder.  This keeps integer divisions, about
+// twenty instructions each, out of the per-element staging loops.
+template <int RY>
+__device__ inline int wrap_row(int gy, int ny)
+{
+    if (ny >= RY) return gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+    return (gy % ny + ny) % ny;
+}
+
 // Stage the index map of plane z (periodic) for the region x in [x0-2, x0+TX+2), y in
 // [y0-2, y0+TY+2) into dst; columns outside the box read -2.
 template <int RX, int RY>
@@ -62,7 +73,7 @@ __device__ inline void stage_plane(const StepArgs& a, int x0, int y0, int z, int
     for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
         const int rx = t % RX, ry = t / RX;
         const int gx = x0 - 2 + rx;
-        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
         dst[t] = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
     }
 }
@@ -82,7 +93,7 @@ __device__ inline void stage_issue(const StepArgs& a, int x0, int y0, int z, Pla
         const int t = threadIdx.x + j * NT;
         const int rx = t % RX, ry = t / RX;
         const int gx = x0 - 2 + rx;
-        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
         r.v[j] = (t < RX * RY && gx >= 0 && gx < a.nx)
                      ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
     }
@@ -105,7 +116,7 @@ __device__ inline void stage_plane_refs(const StepArgs& a, int x0, int y0, int* 
     for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
         const int rx = t % RX, ry = t / RX;
         const int gx = x0 - 2 + rx;
-        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
         const int i = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)((long long)gy * a.nx + gx) * 4u) : -2;
         dst[t] = i;
         sc[t] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
@@ -137,6 +148,86 @@ __device__ inline void gather2d(const StepArgs& a, int i, const int (&si)[L::Q],
 // nodes it needs as halo.  One node per lane keeps the register count low enough for eight
 // waves per SIMD.
 // ---------------------------------------------------------------------------------------------
+// The work of one tile once its index map is staged in sI: the pulls of its own nodes and of its
+// halo, the moments into sX, one barrier, then gradients, the Maxwell-Stefan solve, the collision
+// and the store.  t1 = (own offset, own count, halo offset, halo count) in ent; pe0 / pe2 = this
+// lane's first own and halo entries.  BND: the tile or its halo touches an x face.
+template <class L, int P, bool NS, int TY, int TYR, bool BND>
+__device__ inline void tile_work(const StepArgs& a, int x0, int y0, const int4& t1, unsigned pe0,
+                                 unsigned pe2, const unsigned* __restrict__ ent, const int* sI,
+                                 double (&sX)[2][TYR + 2][64 + 2], const double* sC)
+{
+    using CT = typename Codec<P>::CT;
+    constexpr int TX = 64, RX = TX + 4, RY = TYR + 4, BS = 32 * TY;
+    (void)y0;
+
+    // the lane's own node (at most one: the host splits denser tiles) and its first halo entry:
+    // all loads issued together
+    CT f[2][L::Q];
+    double X0 = 0.0, X1 = 0.0;
+    const int cxo = pe0 & 255u, cyo = pe0 >> 8;
+    const int io = threadIdx.x < (unsigned)t1.y ? sI[(cyo + 1) * RX + cxo + 1] : -1;
+    uint32_t nbo;
+    {
+        const int x = x0 + cxo - 1;
+        int si[L::Q];
+        nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
+        gather2d<L, P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && BND && x == 0, io >= 0 && BND && x == a.nx - 1,
+                                f, X0, X1, sC, cxo + 1, cyo + 1);
+    }
+    if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
+        const int cx = pe2 & 255u, cy = pe2 >> 8;
+        const bool job = threadIdx.x < (unsigned)t1.w;
+        const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
+        const int x = x0 + cx - 1;
+        int si[L::Q];
+        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+        CT hf[2][L::Q];
+        double h0, h1;
+        gather2d<L, P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && BND && x == 0, hi >= 0 && BND && x == a.nx - 1,
+                                hf, h0, h1, sC, cx + 1, cy + 1);
+        if (job) {
+            sX[0][cy][cx] = h0;
+            sX[1][cy][cx] = h1;
+        }
+    }
+    // remaining halo entries (a tile that wraps onto itself in y, or one part of a split tile)
+    for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
+        const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
+        const int cx = pw & 255u, cy = pw >> 8;
+        const int hi = sI[(cy + 1) * RX + cx + 1];
+        const int x = x0 + cx - 1;
+        int si[L::Q];
+        lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
+        CT hf[2][L::Q];
+        double h0, h1;
+        gather2d<L, P, NS, RX, RY>(a, hi, si, BND && x == 0, BND && x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
+        sX[0][cy][cx] = h0;
+        sX[1][cy][cx] = h1;
+    }
+    if (io >= 0) {
+        sX[0][cyo][cxo] = X0;
+        sX[1][cyo][cxo] = X1;
+    }
+    __syncthreads();
+
+    if (io < 0) return;
+    const int cx = cxo, cy = cyo;
+    double g0[3], g1[3];
+    const bool xp = nbo & NB_XP, xm = nbo & NB_XM, yp = nbo & NB_YP, ym = nbo & NB_YM;
+    g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
+    g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
+    g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
+    g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
+    g0[2] = g1[2] = 0.0;
+    double om0, om1;
+    bool hit;
+    ms_relax<2>(a, X0, X1, g0, g1, BND && x0 + cx - 1 == a.nx - 1, om0, om1, hit);
+    if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+    const bool src = x0 + cx - 1 >= a.src_x0;
+    collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
+}
+
 // Global-shift FP32 and 16-bit instantiations fit in 64 VGPRs: ask for eight waves per SIMD for
 // every tile height.  (HIP passes the second launch-bounds argument to the compiler as the
 // minimum number of waves per SIMD, not as CUDA's workgroups per multiprocessor.)
@@ -177,78 +268,10 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
     // Tiles whose nodes and halo touch neither the inlet column nor the outlet column run a copy
     // of the rest with the boundary rules compiled out (a workgroup-uniform branch).
     const bool edge = x0 == 0 || x0 + TX + 1 >= a.nx;
-    auto rest = [&](auto bnd) {
-        constexpr bool BND = decltype(bnd)::value;
-        // the lane's own node (at most one: the host splits denser tiles) and its first halo entry:
-        // all loads issued together
-        CT f[2][L::Q];
-        double X0 = 0.0, X1 = 0.0;
-        const int cxo = pe0 & 255u, cyo = pe0 >> 8;
-        const int io = threadIdx.x < (unsigned)t1.y ? sI[(cyo + 1) * RX + cxo + 1] : -1;
-        uint32_t nbo;
-        {
-            const int x = x0 + cxo - 1;
-            int si[L::Q];
-            nbo = lds_sources<L, RX, RY, 1>(sI, -2, cxo + 1, cyo + 1, x, a.nx, io, si);
-            gather2d<L, P, NS, RX, RY>(a, io < 0 ? 0 : io, si, io >= 0 && BND && x == 0, io >= 0 && BND && x == a.nx - 1,
-                                    f, X0, X1, sC, cxo + 1, cyo + 1);
-        }
-        if ((threadIdx.x & ~63u) < (unsigned)t1.w) {  // wave-uniform: this wave holds halo lanes
-            const int cx = pe2 & 255u, cy = pe2 >> 8;
-            const bool job = threadIdx.x < (unsigned)t1.w;
-            const int hi = job ? sI[(cy + 1) * RX + cx + 1] : -1;
-            const int x = x0 + cx - 1;
-            int si[L::Q];
-            lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
-            CT hf[2][L::Q];
-            double h0, h1;
-            gather2d<L, P, NS, RX, RY>(a, hi < 0 ? 0 : hi, si, hi >= 0 && BND && x == 0, hi >= 0 && BND && x == a.nx - 1,
-                                    hf, h0, h1, sC, cx + 1, cy + 1);
-            if (job) {
-                sX[0][cy][cx] = h0;
-                sX[1][cy][cx] = h1;
-            }
-        }
-        // remaining halo entries (a tile that wraps onto itself in y, or one part of a split tile)
-        for (int e = threadIdx.x + BS; e < t1.w; e += BS) {
-            const unsigned pw = gload<unsigned>(ent, (unsigned)(t1.z + e) * 4u);
-            const int cx = pw & 255u, cy = pw >> 8;
-            const int hi = sI[(cy + 1) * RX + cx + 1];
-            const int x = x0 + cx - 1;
-            int si[L::Q];
-            lds_sources<L, RX, RY, 1>(sI, -2, cx + 1, cy + 1, x, a.nx, hi, si);
-            CT hf[2][L::Q];
-            double h0, h1;
-            gather2d<L, P, NS, RX, RY>(a, hi, si, BND && x == 0, BND && x == a.nx - 1, hf, h0, h1, sC, cx + 1, cy + 1);
-            sX[0][cy][cx] = h0;
-            sX[1][cy][cx] = h1;
-        }
-        if (io >= 0) {
-            sX[0][cyo][cxo] = X0;
-            sX[1][cyo][cxo] = X1;
-        }
-        __syncthreads();
-
-        if (io < 0) return;
-        const int cx = cxo, cy = cyo;
-        double g0[3], g1[3];
-        const bool xp = nbo & NB_XP, xm = nbo & NB_XM, yp = nbo & NB_YP, ym = nbo & NB_YM;
-        g0[0] = grad1(xp, xm, sX[0][cy][cx + 1], X0, sX[0][cy][cx - 1]);
-        g1[0] = grad1(xp, xm, sX[1][cy][cx + 1], X1, sX[1][cy][cx - 1]);
-        g0[1] = grad1(yp, ym, sX[0][cy + 1][cx], X0, sX[0][cy - 1][cx]);
-        g1[1] = grad1(yp, ym, sX[1][cy + 1][cx], X1, sX[1][cy - 1][cx]);
-        g0[2] = g1[2] = 0.0;
-        double om0, om1;
-        bool hit;
-        ms_relax<2>(a, X0, X1, g0, g1, BND && x0 + cx - 1 == a.nx - 1, om0, om1, hit);
-        if (hit) gstore<unsigned>(a.flags, 0u, 1u);
-        const bool src = x0 + cx - 1 >= a.src_x0;
-        collide_store<L, P, NS>(a, io, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
-    };
     if (edge)
-        rest(std::true_type{});
+        tile_work<L, P, NS, TY, TYR, true>(a, x0, y0, t1, pe0, pe2, ent, sI, sX, sC);
     else
-        rest(std::false_type{});
+        tile_work<L, P, NS, TY, TYR, false>(a, x0, y0, t1, pe0, pe2, ent, sI, sX, sC);
 }
 
 // stage_plane for plane z plus, for the NODE shift, the FP64 references of its fluid nodes into
@@ -261,7 +284,7 @@ __device__ inline void stage_plane_refs3d(const StepArgs& a, int x0, int y0, int
     for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
         const int rx = t % RX, ry = t / RX;
         const int gx = x0 - 2 + rx;
-        const int gy = ((y0 - 2 + ry) % a.ny + a.ny) % a.ny;
+        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
         const int i = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
         dst[t] = i;
         sc[t] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
