@@ -42,7 +42,7 @@ BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16")
                   ("D3Q7", "bf16"): 56}
 # the lattice each workload is defined on, and the alternative velocity set it accepts
 WORKLOAD_LATTICES = {"porous_2d": ("D2Q9", "D2Q5"), "porous_3d": ("D3Q19", "D3Q7"),
-                     "batch_2d": ("D2Q9",)}
+                     "batch_2d": ("D2Q9",), "steady": ("D2Q9",)}
 NODE_SHIFT_BYTES = 2 * 8 * 2
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
                   "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
@@ -180,7 +180,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
     ap.add_argument("--shift", default="global", choices=["global", "node"])
-    ap.add_argument("--workload", default="batch_2d", choices=["porous_2d", "porous_3d", "batch_2d"])
+    ap.add_argument("--workload", default="batch_2d",
+                    choices=["porous_2d", "porous_3d", "batch_2d", "steady"])
+    ap.add_argument("--steady-n", type=int, default=32, help="steady workload: instances")
+    ap.add_argument("--steady-side", type=int, default=96, help="steady workload: slice side")
+    ap.add_argument("--steady-tol", type=float, default=1e-8, help="steady workload: residual")
     ap.add_argument("--lattice", default="", choices=["", "d2q9", "d2q5", "d3q19", "d3q7"],
                     help="velocity set: d2q9 (default) or d2q5 for porous_2d, d3q19 (default) or "
                          "d3q7 for porous_3d")
@@ -205,6 +209,11 @@ def main(argv=None):
 
     from paper_1809_01600_amd import inputs, lbm_ms
 
+    if args.workload == "steady":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        return run_steady(args)
     if args.workload == "batch_2d":
         cases = inputs.batch_2d(tau_ref=3.0,
                                 accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
@@ -396,6 +405,77 @@ def run_batch(args, cases, cpu):
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     b.close()
+    return 0
+
+
+def run_steady(args):
+    """Steady solves per second at a residual tolerance: the batched, warm-started, reduced-
+    precision form (one batched job, the network's BF16 prediction as the start, FP16 storage
+    with the NODE shift) against the plain FP32 form (one instance at a time from the channel
+    composition), on porous slices drawn like the warm-start evaluation (X_in ~ Dirichlet(6,3,1),
+    j ~ U[0, 2] A/cm^2, tau_ref 3), each overpotential compared with an FP64 reference converged to
+    r = 1e-11.  The network is first trained by the library's kernels on 256 steady 64^2 slices
+    the method generates (its time is reported, not counted in the solves)."""
+    import numpy as np
+    import torch
+    from paper_1809_01600_amd import cnn, lbm_ms, warmstart
+    quiet = lambda m: None  # noqa: E731
+    t0 = time.perf_counter()
+    feat, tgt, fluid = warmstart.generate(256, 64, 50000, chunk=128, tol=1e-9, log=quiet)
+    net = cnn.WarmStartNet(seed=0)
+    warmstart.train(net, feat, tgt, fluid, epochs=12, batch=16, lr=2e-3, log=quiet)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del feat, tgt, fluid
+    cases = warmstart.make_cases(args.steady_n, args.steady_side, 60000)
+    ref, _, _ = warmstart.solve(cases, tol=1e-11, precision="fp64", max_steps=8_000_000)
+    keep = [k for k in range(len(cases)) if ref.status[k] == 0]
+    eta_ref = ref.overpotential()[keep]
+    ref.close()
+    cases = [cases[k] for k in keep]
+    tol = args.steady_tol
+    st_p, stat_p, eta_p, sec_p = warmstart.solve_plain(cases, tol=tol, precision="fp32")
+    fast, st_f, sec_f = warmstart.solve(cases, X0=warmstart.cnn_start(net, cases), tol=tol,
+                                        precision="fp16", shift_mode=lbm_ms.SHIFT_NODE)
+    eta_f = fast.overpotential()
+    ok_f = int(np.sum(fast.status == 0))
+    fast.close()
+    n = len(cases)
+    line = {
+        "metric": METRIC,
+        "value": round(n / sec_f, 3),
+        "unit": "steady solves/s",
+        "n_gpus": 1,
+        "steps": int(st_f.sum()),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {
+            "workload": "%d porous slices D2Q9 %dx%d, void fraction ~U[0.3,0.5], disks r~U[3,12], "
+                        "X_in~Dirichlet(6,3,1), j~U[0,2] A/cm^2, tau_ref 3, seeds 60000+, steady "
+                        "solves to r=%g" % (n, args.steady_side, args.steady_side, tol),
+            "fast_form": "one batched job, CNN warm start (BF16 inference), FP16 NODE-shift storage",
+            "plain_form": "one instance at a time, uniform start, FP32 storage",
+            "plain_solves_per_s": round(n / sec_p, 3),
+            "speedup_vs_plain": round(sec_p / sec_f, 2),
+            "fast_seconds": round(sec_f, 3),
+            "plain_seconds": round(sec_p, 3),
+            "fast_converged": ok_f,
+            "plain_converged": int(np.sum(stat_p == 0)),
+            "fast_mean_steps": float(st_f.mean()),
+            "plain_mean_steps": float(st_p.mean()),
+            "fast_max_abs_eta_err_V": float(np.nanmax(np.abs(eta_f - eta_ref))),
+            "plain_max_abs_eta_err_V": float(np.nanmax(np.abs(eta_p - eta_ref))),
+            "reference": "FP64 batched, r=1e-11",
+            "network_training_s": round(train_s, 1),
+            "parallelism": "single GPU",
+        },
+    }
+    print(json.dumps(line), flush=True)
     return 0
 
 
