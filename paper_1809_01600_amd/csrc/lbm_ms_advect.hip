@@ -119,13 +119,8 @@ __device__ inline void ms_relax_adv(const StepArgs& a, const AdvArgs& v, double 
         w[i] = inv / (3.0 + 0.5 * inv);
     }
     bool h = false;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        if (!(w[i] <= a.om_hi)) { w[i] = a.om_hi; h = true; }
-        else if (w[i] < a.om_lo) { w[i] = a.om_lo; h = true; }
-    }
-    om0 = w[0];
-    om1 = w[1];
+    om0 = clamp_omega(a, w[0], h);
+    om1 = clamp_omega(a, w[1], h);
     hit = h;
 }
 

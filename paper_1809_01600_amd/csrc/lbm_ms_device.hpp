@@ -526,6 +526,22 @@ struct MsMat {
     double B00, B01, B10, B11, rdet;
 };
 
+// The clamp of tau to [tau_min, tau_max], applied to w = 1/tau: a tau below tau_min, a negative
+// one included (1/D in (-6, 0) gives w < 0), becomes tau_min, and one above tau_max becomes
+// tau_max; a non-finite w counts as below tau_min.  Sets h when it applies.
+__device__ inline double clamp_omega(const StepArgs& a, double w, bool& h)
+{
+    if (!(w <= a.om_hi) || __builtin_signbit(w)) {
+        h = true;
+        return a.om_hi;
+    }
+    if (w < a.om_lo) {
+        h = true;
+        return a.om_lo;
+    }
+    return w;
+}
+
 template <bool RDET>
 __device__ inline MsMat ms_matrix(const StepArgs& a, double X0, double X1)
 {
@@ -578,18 +594,11 @@ __device__ inline void ms_relax(const StepArgs& a, double X0, double X1, const M
     // Eq. 24 with N_i = sigma_i |N_i|; the inert species (sigma = 0) contributes X_3 / D_i3
     const double inv0 = (X1 - X0 * a.sgn12 * r21) * a.iD12 + X2 * a.iD13;
     const double inv1 = (X0 - X1 * a.sgn12 * r12) * a.iD12 + X2 * a.iD23;
-    // Eq. 25 with c_s^2 = 1/3: tau = 3 D + 1/2, so 1/tau = (1/D) / (3 + (1/D) / 2); the clamp
-    // tau in [tau_min, tau_max] is applied as 1/tau in [1/tau_max, 1/tau_min]
-    double w0 = inv0 * rcp64(3.0 + 0.5 * inv0);
-    double w1 = inv1 * rcp64(3.0 + 0.5 * inv1);
+    // Eq. 25 with c_s^2 = 1/3: tau = 3 D + 1/2, so 1/tau = (1/D) / (3 + (1/D) / 2), clamped
     bool h = false;
-    if (!(w0 <= a.om_hi)) { w0 = a.om_hi; h = true; }
-    else if (w0 < a.om_lo) { w0 = a.om_lo; h = true; }
-    if (!(w1 <= a.om_hi)) { w1 = a.om_hi; h = true; }
-    else if (w1 < a.om_lo) { w1 = a.om_lo; h = true; }
+    om0 = clamp_omega(a, inv0 * rcp64(3.0 + 0.5 * inv0), h);
+    om1 = clamp_omega(a, inv1 * rcp64(3.0 + 0.5 * inv1), h);
     hit = h;
-    om0 = w0;
-    om1 = w1;
 }
 
 template <int DIMS>
