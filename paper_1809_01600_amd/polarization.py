@@ -20,10 +20,16 @@ from . import autotune, inputs, lbm_ms
 
 
 def curve(count=64, side_lo=64, side_hi=256, j_hi=2.0, tau_ref=3.0, tol=1e-9, precision="fp32",
-          shift="node", max_steps=8_000_000, check_every=1000, chunk=500_000, log=print):
+          shift="node", max_steps=8_000_000, check_every=1000, chunk=500_000, subset=0, log=print):
+    """subset > 0 keeps that many of the `count` drawn instances, evenly spaced in side length
+    (the drawn batch sorted by side), so a shorter job still spans the size range."""
     import torch
     cases = inputs.batch_2d(count=count, side_lo=side_lo, side_hi=side_hi, j_hi=j_hi, tau_ref=tau_ref,
                             accept=lambda solid: lbm_ms.clean_geometry("D2Q9", solid)[1] > 0)
+    if 0 < subset < count:
+        by_side = sorted(range(count), key=lambda k: (cases[k].nx, k))
+        cases = [cases[by_side[(i * count) // subset + count // (2 * subset)]] for i in range(subset)]
+        count = subset
     b = lbm_ms.Batch(cases, precision=precision, ms_mode=lbm_ms.STOICH,
                      shift_mode=lbm_ms.SHIFT_NODE if shift == "node" else lbm_ms.SHIFT_GLOBAL)
     tile = autotune.tune_batch(b)
@@ -63,13 +69,16 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--shift", default="node", choices=["node", "global"])
+    ap.add_argument("--subset", type=int, default=0,
+                    help="keep this many of the drawn instances, evenly spaced in side")
+    ap.add_argument("--max-steps", type=int, default=8_000_000)
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     res = curve(args.count, args.side_lo, args.side_hi, args.j_hi, tol=args.tol,
-                precision=args.precision, shift=args.shift,
-                log=lambda m: print(m, flush=True))
+                precision=args.precision, shift=args.shift, max_steps=args.max_steps,
+                subset=args.subset, log=lambda m: print(m, flush=True))
     print(json.dumps({k: v for k, v in res.items() if k != "curve"}), flush=True)
     for r in res["curve"]:
         print("j %.4f A/cm2  side %4d  eta %.6f V  steps %8d  status %d"
