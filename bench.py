@@ -315,7 +315,8 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step3d" if case.nz > 1 else "k_step2d",
+            "kernel": ("k_step3dc" if int(info.tile_y) in (12, 16) else "k_step3d") if case.nz > 1
+                      else "k_step2d",
             "kernel_us": round(kernel_ms * 1e3, 3),
             "bytes_per_launch": bytes_per_launch,
         },

@@ -264,12 +264,17 @@ int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w);
 int lbm_ms_work_list(int lattice, int nx, int ny, const uint8_t* solid, int tile_y, int rows,
                      int64_t* n_tiles, int64_t* n_ent, int32_t* tiles, uint32_t* ent);
 
-/* Launch shapes compiled for a lattice: writes up to cap (tile_y, chunk_z) pairs, returns the
- * count.  3D: 64 x tile_y columns marching chunk_z planes.  2D: workgroups of 32 tile_y lanes,
- * one fluid node per lane; chunk_z = 0 for fixed 64 x tile_y tiles (a denser tile is split into
- * parts), chunk_z > 0 for packed tiles that grow row by row in each 64-wide strip up to chunk_z
- * rows or 32 tile_y fluid nodes. */
-int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap);
+/* Launch shapes compiled for a lattice and storage mode (precision, shift_mode): writes up to cap
+ * (tile_y, chunk_z) pairs, returns the count (at most 16).  3D: 64 x tile_y columns marching
+ * chunk_z planes; tile_y 4 and 8 give each lane one voxel of a 64 x tile_y plane, tile_y 12 and 16
+ * (global-shift storage in FP32, FP16 or BF16 only) give the 512 lanes of a workgroup the fluid
+ * voxels of a 64 x tile_y plane in order, from per-(column, plane) lists that the handle builds at
+ * lbm_ms_set_geometry and lbm_ms_set_tile (2 bytes per fluid node).  2D: workgroups of 32 tile_y
+ * lanes, one fluid node per lane; chunk_z = 0 for fixed 64 x tile_y tiles (a denser tile is split
+ * into parts), chunk_z > 0 for packed tiles that grow row by row in each 64-wide strip up to
+ * chunk_z rows or 32 tile_y fluid nodes. */
+int lbm_ms_tile_options(int lattice, int precision, int shift_mode, int* tile_y, int* chunk_z,
+                        int cap);
 
 /* Change the launch shape of an existing handle (one of lbm_ms_tile_options). */
 int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z);

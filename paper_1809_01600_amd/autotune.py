@@ -87,7 +87,7 @@ def tune(solver, steps: int = 100, warmup: int = 10, use_cache: bool = True):
         return tuple(data[key]["tile"])
     blob = solver.save_state()
     timings = {}
-    for ty, cz in lbm_ms.tile_options(p.lattice, p.precision):
+    for ty, cz in lbm_ms.tile_options(p.lattice, p.precision, p.shift_mode):
         solver.set_tile(ty, cz)
         solver.step(warmup)
         timings[(ty, cz)] = solver.time_steps(steps) / steps
@@ -116,7 +116,7 @@ def tune_batch(batch, steps: int = 20, warmup: int = 3, use_cache: bool = True):
         return tuple(data[key]["tile"])
     timings = {}
     batch.init()
-    for ty, rows in lbm_ms.tile_options(p.lattice, p.precision):
+    for ty, rows in lbm_ms.tile_options(p.lattice, p.precision, p.shift_mode):
         batch.set_tile(ty, rows)
         batch.step(warmup)
         timings[(ty, rows)] = batch.time_steps(steps) / steps

@@ -6,9 +6,10 @@
 // (recomputed from the halo nodes' own pulls), solves the Maxwell-Stefan system in FP64 for the
 // relaxation times, collides and stores to the other buffer.  Populations of fluid nodes only
 // are stored, structure of arrays [species][link][fluid node] with the fluid nodes numbered in
-// raster order (x fastest); a dense int32 map gives each voxel's fluid index (-1 = solid), so
-// solid voxels cost no population traffic while a wavefront's loads and stores stay contiguous
-// along x.
+// raster order (x fastest) in 2D and, in 3D, column by column of 64 x 16 voxels, plane by plane
+// and in raster order within a plane; a dense int32 map gives each voxel's fluid index (-1 =
+// solid), so solid voxels cost no population traffic while a wavefront's loads and stores stay
+// contiguous along x.
 #include <hip/hip_runtime.h>
 #include <type_traits>
 
@@ -516,6 +517,224 @@ __global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k
 }
 
 // ---------------------------------------------------------------------------------------------
+// 3D over fluid-compacted planes (global-shift storage, 32- and 16-bit populations).  A workgroup
+// owns a column of 64 x TY voxels (TY = 12 or 16) and marches CZ planes like k_step3d, but its
+// 512 lanes take the fluid voxels of each plane in order, from a per-(column, plane) list of
+// in-column positions built on the host, instead of one voxel each.  In a porous block about half
+// the voxels are solid, so a plane of a 64 x 16 column fills about as many lanes as a 64 x 8
+// plane leaves idle, and each wave's loads and FP64 solves carry twice the nodes.
+//
+// A plane with more fluid voxels than lanes hands the rest to a second pass: moments only before
+// the barrier (the z gradients of the plane below need them), pulled again and collided after it.
+// A lane's voxel moves from plane to plane, so z gradients come from the moment ring in LDS, four
+// planes deep (below, own, above, and the one the next iteration writes), and the index ring
+// holds six planes (a second-pass pull after the barrier still reads the planes around its own
+// while the next iteration stages a new one).
+// ---------------------------------------------------------------------------------------------
+template <class L, int P, int TY, int CZ>
+__global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* __restrict__ coff,
+                                                    const unsigned short* __restrict__ cpos)
+{
+    using CT = typename Codec<P>::CT;
+    using raw = typename Codec<P>::raw;
+    constexpr int NT = 512, TX = 64, RX = TX + 4, RY = TY + 4, NPL = 6;
+    constexpr int NHALO = 2 * TX + 2 * TY;
+    constexpr int HWAVES = (NHALO + 63) / 64;
+    static_assert(TX * TY <= 2 * NT, "at most two passes per plane");
+    __shared__ int sI[NPL * RY * RX];
+    __shared__ double sX[4][2][TY + 2][TX + 2];  // moment ring: relative plane r in slot (r + 1) & 3
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = tile % a.tiles_x;
+    const int rest = tile / a.tiles_x;
+    const int by = rest % a.tiles_y;
+    const int bz = rest / a.tiles_y;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * CZ;
+    // plane offsets of this column: plane z holds positions [col[z], col[z + 1]) of cpos
+    const unsigned* col = coff + (size_t)(bx + a.tiles_x * by) * a.nz;
+    const int l = threadIdx.x;
+    int hx = 0, hy = 0;
+    halo_pos<TX, TY>(l, hx, hy);
+    // The lists hold the column's rows inside the box only, so the row above a column cut short
+    // by the box edge (y0 + TY > ny) belongs to the halo: that row of the staged region wraps to
+    // y = 0, and its moments go where the column's last row looks for its +y neighbour.
+    const int rows = a.ny - y0 < TY ? a.ny - y0 : TY;
+    if (hy == TY) hy = rows;
+    const int hgx = x0 + hx;
+    const bool hjob = l < NHALO && hgx >= 0 && hgx < a.nx && hy <= rows;
+    auto plane_of = [&](int r, unsigned& start, int& count) {  // list of relative plane r
+        const int zw = ((z0 + r) % a.nz + a.nz) % a.nz;
+        start = col[zw];
+        count = (int)(col[zw + 1] - start);
+    };
+    auto index_at = [&](int r, int cx, int cy) { return sI[(((r + 2) % NPL) * RY + cy + 2) * RX + cx + 2]; };
+    // moments of the fluid voxel at (cx, cy) of relative plane r into the ring
+    auto moments_to_ring = [&](int r, int p) {
+        const int cx = p & 63, cy = p >> 6, x = x0 + cx;
+        const int i = index_at(r, cx, cy);
+        int si[L::Q];
+        lds_sources<L, RX, RY, NPL>(sI, r, cx + 2, cy + 2, x, a.nx, i, si);
+        CT f[2][L::Q];
+        double X0, X1;
+        gather<L, P, false>(a, i, si, x == 0, x == a.nx - 1, f, X0, X1);
+        sX[(r + 1) & 3][0][cy + 1][cx + 1] = X0;
+        sX[(r + 1) & 3][1][cy + 1][cx + 1] = X1;
+    };
+    // Eq. 24-25 from the ring: x, y gradients in the node's plane r, z from the planes around it
+    auto relax = [&](int r, int cx, int cy, uint32_t nb, double X0, double X1, bool outlet,
+                     double& om0, double& om1) {
+        const int s = (r + 1) & 3, su = (r + 2) & 3, sd = r & 3;
+        const int px = cx + 1, py = cy + 1;
+        double g0[3], g1[3];
+        const bool xp = nb & NB_XP, xm = nb & NB_XM, yp = nb & NB_YP, ym = nb & NB_YM;
+        const bool zp = nb & NB_ZP, zm = nb & NB_ZM;
+        g0[0] = grad1(xp, xm, sX[s][0][py][px + 1], X0, sX[s][0][py][px - 1]);
+        g1[0] = grad1(xp, xm, sX[s][1][py][px + 1], X1, sX[s][1][py][px - 1]);
+        g0[1] = grad1(yp, ym, sX[s][0][py + 1][px], X0, sX[s][0][py - 1][px]);
+        g1[1] = grad1(yp, ym, sX[s][1][py + 1][px], X1, sX[s][1][py - 1][px]);
+        g0[2] = grad1(zp, zm, sX[su][0][py][px], X0, sX[sd][0][py][px]);
+        g1[2] = grad1(zp, zm, sX[su][1][py][px], X1, sX[sd][1][py][px]);
+        bool hit;
+        ms_relax<3>(a, X0, X1, g0, g1, outlet, om0, om1, hit);
+        if (hit) gstore<unsigned>(a.flags, 0u, 1u);
+    };
+
+    for (int zr = -2; zr <= 2; ++zr) stage_plane<RX, RY>(a, x0, y0, z0 + zr, sI + ((zr + 2) % NPL) * RY * RX);
+    __syncthreads();
+
+    // plane z0-1: moments of every fluid voxel (z gradients of plane z0)
+    unsigned st;
+    int cnt;
+    plane_of(-1, st, cnt);
+    for (int k = l; k < cnt; k += NT) moments_to_ring(-1, cpos[st + k]);
+    // plane z0: the first pass keeps its populations, a second pass and the halo ring give moments
+    CT fc[2][L::Q];
+    int ic = -1, pc = 0;
+    uint32_t nbc = 0;
+    double Xc0 = 0.0, Xc1 = 0.0;
+    plane_of(0, st, cnt);
+    int cnt_c = cnt;
+    unsigned st_c = st;
+    if (l < cnt) {
+        pc = cpos[st + l];
+        const int cx = pc & 63, cy = pc >> 6, x = x0 + cx;
+        ic = index_at(0, cx, cy);
+        int si[L::Q];
+        nbc = lds_sources<L, RX, RY, NPL>(sI, 0, cx + 2, cy + 2, x, a.nx, ic, si);
+        gather<L, P, false>(a, ic, si, x == 0, x == a.nx - 1, fc, Xc0, Xc1);
+        sX[1][0][cy + 1][cx + 1] = Xc0;
+        sX[1][1][cy + 1][cx + 1] = Xc1;
+    }
+    for (int k = l + NT; k < cnt; k += NT) moments_to_ring(0, cpos[st + k]);
+    // the list of plane z0+1 and this lane's first-pass position in it, one plane ahead of use
+    unsigned st_n;
+    int cnt_n;
+    plane_of(1, st_n, cnt_n);
+    int p_n = l < cnt_n ? cpos[st_n + l] : 0;
+    if (l < HWAVES * 64) {
+        const int hi = hjob ? index_at(0, hx, hy) : -1;
+        int hsi[L::Q];
+        lds_sources<L, RX, RY, NPL>(sI, 0, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
+        CT hf[2][L::Q];
+        double h0, h1;
+        gather<L, P, false>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+        if (l < NHALO) {
+            sX[1][0][hy + 1][hx + 1] = hi < 0 ? 0.0 : h0;
+            sX[1][1][hy + 1][hx + 1] = hi < 0 ? 0.0 : h1;
+        }
+    }
+    __syncthreads();
+
+    for (int it = 0; it < CZ; ++it) {
+        const int zi = z0 + it;
+        if (zi >= a.nz) break;  // uniform across the workgroup
+        PlaneRegs<RX, RY, NT> stg;
+        stage_issue<RX, RY, NT>(a, x0, y0, z0 + it + 3, stg);
+        const int r = it + 1;
+        const bool need_next = (it + 1 < CZ) && (zi + 1 < a.nz);
+        st = st_n;
+        cnt = cnt_n;
+        const int pn = p_n;
+        plane_of(r + 1, st_n, cnt_n);
+        p_n = l < cnt_n ? cpos[st_n + l] : 0;
+        // first pass of plane it+1 (populations kept) and, if it is output, its halo ring; all
+        // loads issued before any is used
+        const bool own_n = l < cnt;
+        const int cxn = pn & 63, cyn = pn >> 6, xn = x0 + cxn;
+        const int in_ = own_n ? index_at(r, cxn, cyn) : -1;
+        int si[L::Q];
+        const uint32_t nbn = lds_sources<L, RX, RY, NPL>(sI, r, cxn + 2, cyn + 2, xn, a.nx, in_, si);
+        const bool hwave = need_next && l < HWAVES * 64;  // uniform per wave
+        const int hi = (hwave && hjob) ? index_at(r, hx, hy) : -1;
+        CT fn[2][L::Q];
+        double Xp0, Xp1, h0 = 0.0, h1 = 0.0;
+        {
+            raw rn[2][L::Q], rh[2][L::Q];
+            gather_issue<L, P>(a, in_ < 0 ? 0 : in_, si, xn == 0, xn == a.nx - 1, rn);
+            if (hwave) {
+                int hsi[L::Q];
+                lds_sources<L, RX, RY, NPL>(sI, r, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
+                gather_issue<L, P>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, rh);
+            }
+            gather_finish<L, P>(a, rn, xn == 0, xn == a.nx - 1, fn, Xp0, Xp1);
+            if (hwave) {
+                CT hf[2][L::Q];
+                gather_finish<L, P>(a, rh, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+            }
+        }
+        if (in_ < 0) Xp0 = Xp1 = 0.0;
+        if (hi < 0) h0 = h1 = 0.0;
+        const int sn = (r + 1) & 3;
+        if (own_n) {
+            sX[sn][0][cyn + 1][cxn + 1] = Xp0;
+            sX[sn][1][cyn + 1][cxn + 1] = Xp1;
+        }
+        if (hwave && l < NHALO) {
+            sX[sn][0][hy + 1][hx + 1] = h0;
+            sX[sn][1][hy + 1][hx + 1] = h1;
+        }
+        // second pass of plane it+1: moments only
+        for (int k = l + NT; k < cnt; k += NT) moments_to_ring(r, cpos[st + k]);
+        stage_store<RX, RY, NT>(stg, sI + (it + 5) % NPL * RY * RX);
+        __syncthreads();
+        // collision of plane it: the kept first pass ...
+        if (ic >= 0) {
+            const int cx = pc & 63, cy = pc >> 6, x = x0 + cx;
+            double om0, om1;
+            relax(it, cx, cy, nbc, Xc0, Xc1, x == a.nx - 1, om0, om1);
+            const bool src = x >= a.src_x0;
+            collide_store<L, P, false>(a, ic, fc, Xc0, Xc1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
+        }
+        // ... and the second pass, pulled again
+        for (int k = l + NT; k < cnt_c; k += NT) {
+            const int p = cpos[st_c + k];
+            const int cx = p & 63, cy = p >> 6, x = x0 + cx;
+            const int i = index_at(it, cx, cy);
+            int ssi[L::Q];
+            const uint32_t nb = lds_sources<L, RX, RY, NPL>(sI, it, cx + 2, cy + 2, x, a.nx, i, ssi);
+            CT f[2][L::Q];
+            double X0, X1, om0, om1;
+            gather<L, P, false>(a, i, ssi, x == 0, x == a.nx - 1, f, X0, X1);
+            relax(it, cx, cy, nb, X0, X1, x == a.nx - 1, om0, om1);
+            const bool src = x >= a.src_x0;
+            collide_store<L, P, false>(a, i, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
+        }
+        ic = in_;
+        pc = pn;
+        nbc = nbn;
+        Xc0 = Xp0;
+        Xc1 = Xp1;
+        cnt_c = cnt;
+        st_c = st;
+#pragma unroll
+        for (int k = 0; k < L::Q; ++k) {
+            fc[0][k] = fn[0][k];
+            fc[1][k] = fn[1][k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // initial state: f*_a = w_a X (equilibrium), optionally from a [3][N] FP64 field
 // ---------------------------------------------------------------------------------------------
 template <class L, int P, bool NS>
@@ -868,8 +1087,23 @@ struct Ops {
 };
 
 template <class L, int P, bool NS>
-static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int cz, int nblocks)
+static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int cz, int nblocks,
+                                const unsigned* coff, const unsigned short* cpos)
 {
+    if (ty == 12 || ty == 16) {
+        if constexpr (NS || P == P_F64) {
+            return hipErrorInvalidValue;
+        } else {
+            if (!coff || !cpos) return hipErrorInvalidValue;
+            if (ty == 12 && cz == 32) hipLaunchKernelGGL((k_step3dc<L, P, 12, 32>), dim3(nblocks), dim3(512), 0, st, a, coff, cpos);
+            else if (ty == 12 && cz == 64) hipLaunchKernelGGL((k_step3dc<L, P, 12, 64>), dim3(nblocks), dim3(512), 0, st, a, coff, cpos);
+            else if (ty == 16 && cz == 16) hipLaunchKernelGGL((k_step3dc<L, P, 16, 16>), dim3(nblocks), dim3(512), 0, st, a, coff, cpos);
+            else if (ty == 16 && cz == 32) hipLaunchKernelGGL((k_step3dc<L, P, 16, 32>), dim3(nblocks), dim3(512), 0, st, a, coff, cpos);
+            else if (ty == 16 && cz == 64) hipLaunchKernelGGL((k_step3dc<L, P, 16, 64>), dim3(nblocks), dim3(512), 0, st, a, coff, cpos);
+            else return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+    }
     if (ty == 4 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 4, 16>), dim3(nblocks), dim3(256), 0, st, a);
     else if (ty == 4 && cz == 32) hipLaunchKernelGGL((k_step3d<L, P, NS, 4, 32>), dim3(nblocks), dim3(256), 0, st, a);
     else if (ty == 8 && cz == 16) hipLaunchKernelGGL((k_step3d<L, P, NS, 8, 16>), dim3(nblocks), dim3(512), 0, st, a);
@@ -882,10 +1116,10 @@ static hipError_t launch_step_l(hipStream_t st, const StepArgs& a, int ty, int c
 
 template <int P, bool NS>
 static hipError_t launch_step_p(hipStream_t st, const StepArgs& a, int lattice, int ty, int cz,
-                                int nblocks)
+                                int nblocks, const unsigned* coff, const unsigned short* cpos)
 {
-    if (lattice == 1) return launch_step_l<D3Q19, P, NS>(st, a, ty, cz, nblocks);
-    if (lattice == 3) return launch_step_l<D3Q7, P, NS>(st, a, ty, cz, nblocks);
+    if (lattice == 1) return launch_step_l<D3Q19, P, NS>(st, a, ty, cz, nblocks, coff, cpos);
+    if (lattice == 3) return launch_step_l<D3Q7, P, NS>(st, a, ty, cz, nblocks, coff, cpos);
     return hipErrorInvalidValue;
 }
 
@@ -935,14 +1169,16 @@ hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tile
     return hipErrorInvalidValue;
 }
 
-int tile_options(int lattice, int* ty, int* cz, int cap)
+int tile_options(int lattice, bool compacted, int* ty, int* cz, int cap)
 {
     // 2D: (lanes / 32, 0) for fixed 64 x TY tiles, (lanes / 32, rows) for packed tiles of at
-    // most `rows` rows; 3D: (TY, planes per workgroup)
+    // most `rows` rows; 3D: (TY, planes per workgroup), TY = 12 and 16 for the fluid-compacted
+    // columns (global-shift storage in 32 or 16 bits only)
     static const int t2[5][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 9}, {8, 12}};
-    static const int t3[6][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}, {8, 128}};
+    static const int t3[11][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}, {8, 128},
+                                  {12, 32}, {12, 64}, {16, 16}, {16, 32}, {16, 64}};
     const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
-    const int total = d2 ? 5 : 6;
+    const int total = d2 ? 5 : (compacted ? 11 : 6);
     for (int i = 0; i < total && i < cap; ++i) {
         if (ty) ty[i] = d2 ? t2[i][0] : t3[i][0];
         if (cz) cz[i] = d2 ? t2[i][1] : t3[i][1];
@@ -959,6 +1195,10 @@ static int resident3d_l(int ty)
     hipError_t e = hipErrorInvalidValue;
     if (ty == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<L, P, NS, 4, 32>, 256, 0);
     else if (ty == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<L, P, NS, 8, 32>, 512, 0);
+    if constexpr (!NS && P != P_F64) {
+        if (ty == 12) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3dc<L, P, 12, 32>, 512, 0);
+        else if (ty == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3dc<L, P, 16, 32>, 512, 0);
+    }
     return e == hipSuccess ? n : 0;
 }
 
@@ -982,16 +1222,16 @@ int step3d_resident_blocks(int lattice, int prec, int node_shift, int ty)
 }
 
 hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,
-                       int ty, int cz, int nblocks)
+                       int ty, int cz, int nblocks, const unsigned* coff, const unsigned short* cpos)
 {
     switch (prec) {
-    case P_F64: return launch_step_p<P_F64, false>(st, a, lattice, ty, cz, nblocks);
-    case P_F32: return node_shift ? launch_step_p<P_F32, true>(st, a, lattice, ty, cz, nblocks)
-                                  : launch_step_p<P_F32, false>(st, a, lattice, ty, cz, nblocks);
-    case P_F16: return node_shift ? launch_step_p<P_F16, true>(st, a, lattice, ty, cz, nblocks)
-                                  : launch_step_p<P_F16, false>(st, a, lattice, ty, cz, nblocks);
-    case P_BF16: return node_shift ? launch_step_p<P_BF16, true>(st, a, lattice, ty, cz, nblocks)
-                                   : launch_step_p<P_BF16, false>(st, a, lattice, ty, cz, nblocks);
+    case P_F64: return launch_step_p<P_F64, false>(st, a, lattice, ty, cz, nblocks, coff, cpos);
+    case P_F32: return node_shift ? launch_step_p<P_F32, true>(st, a, lattice, ty, cz, nblocks, coff, cpos)
+                                  : launch_step_p<P_F32, false>(st, a, lattice, ty, cz, nblocks, coff, cpos);
+    case P_F16: return node_shift ? launch_step_p<P_F16, true>(st, a, lattice, ty, cz, nblocks, coff, cpos)
+                                  : launch_step_p<P_F16, false>(st, a, lattice, ty, cz, nblocks, coff, cpos);
+    case P_BF16: return node_shift ? launch_step_p<P_BF16, true>(st, a, lattice, ty, cz, nblocks, coff, cpos)
+                                   : launch_step_p<P_BF16, false>(st, a, lattice, ty, cz, nblocks, coff, cpos);
     }
     return hipErrorInvalidValue;
 }

@@ -7,11 +7,14 @@
 
 namespace lbmms {
 
-int tile_options(int lattice, int* ty, int* cz, int cap);
+// compiled launch shapes of a lattice; `compacted` adds the 3D fluid-compacted columns (TY 12, 16)
+int tile_options(int lattice, bool compacted, int* ty, int* cz, int cap);
 // workgroups of the 3D step (64 x ty columns) resident per CU on the current device, 0 on error
 int step3d_resident_blocks(int lattice, int prec, int node_shift, int ty);
+// 3D step; ty 12 and 16 select the fluid-compacted columns, which read the per-(column, plane)
+// fluid lists coff / cpos (global-shift storage in 32 or 16 bits)
 hipError_t launch_step(hipStream_t st, const StepArgs& a, int lattice, int prec, int node_shift,
-                       int ty, int cz, int nblocks);
+                       int ty, int cz, int nblocks, const unsigned* coff, const unsigned short* cpos);
 // 2D work-list step: insts = instance table of this step's parity, tiles = 2 int4 per tile;
 // 32 ty lanes per workgroup, rows = 0 for fixed 64 x ty tiles, else the packed tiles' row limit
 hipError_t launch_step2d(hipStream_t st, const StepArgs* insts, const int4* tiles,

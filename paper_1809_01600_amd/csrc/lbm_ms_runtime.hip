@@ -23,12 +23,13 @@ namespace {
 constexpr double R_GAS = 8.3145;    // J / (mol K)
 constexpr double FARADAY = 96485.0; // C / mol (Eq. 39)
 constexpr int RED_BLOCKS = 1024;    // per-block partials of the reductions
-constexpr uint64_t STATE_MAGIC = 0x314d534c42304c31ull;
+constexpr uint64_t STATE_MAGIC = 0x324d534c42304c31ull;
 
 struct Layout {
     size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
     size_t tile_cap, ent_cap;
     size_t g[2], u[2], xa;  // advective coupling: velocity model, node velocities, X per node
+    size_t c3off, c3pos;    // 3D fluid-compacted columns: plane offsets, in-column positions
 };
 
 int q_of(int lattice)
@@ -64,6 +65,54 @@ void tile_caps(int nx, int ny, size_t* tiles, size_t* ents)
 bool node_shift(const lbm_ms_params& p)
 {
     return p.precision != LBM_MS_FP64 && p.shift_mode == LBM_MS_SHIFT_NODE;
+}
+
+// the 3D fluid-compacted columns (launch shapes with tile_y 12 and 16) are built for global-shift
+// storage in 32 or 16 bits
+bool compacted3d(int lattice, int precision, int shift_mode)
+{
+    return !is_2d(lattice) && precision != LBM_MS_FP64 && shift_mode == LBM_MS_SHIFT_GLOBAL;
+}
+bool compacted3d(const lbm_ms_params& p) { return compacted3d(p.lattice, p.precision, p.shift_mode); }
+bool compacted_ty(int ty) { return ty == 12 || ty == 16; }
+
+// Visit the voxels of the 3D column plane with origin (x0, y0) and ylen rows in the order its
+// fluid nodes are numbered: the two edge lines x = x0 and x = x0 + 63 first (y increasing),
+// then the rows between in raster order.
+constexpr int COL_X = 64, COL_Y = 16;
+template <class Visit>
+void column_plane_order(int nx, int ny, int x0, int y0, int ylen, Visit&& visit)
+{
+    const int x1 = std::min(x0 + COL_X, nx) - 1;  // last column of the box, or x0 + 63
+    for (int y = y0; y < y0 + ylen && y < ny; ++y) visit(x0, y);
+    if (x1 > x0)
+        for (int y = y0; y < y0 + ylen && y < ny; ++y) visit(x1, y);
+    for (int y = y0; y < y0 + ylen && y < ny; ++y)
+        for (int x = x0 + 1; x < x1; ++x) visit(x, y);
+}
+
+// Plane lists of the fluid-compacted 3D columns: for column c = bx + tiles_x by (64 x ty voxels)
+// and plane z, the in-column positions lx + 64 ly of its fluid voxels, in the order the fluid
+// nodes are numbered (column_plane_order), are pos[off[c nz + z], off[c nz + z + 1]); off has
+// tiles_x tiles_y nz + 1 entries.
+void build_cols_3d(int nx, int ny, int nz, int ty, const std::vector<uint8_t>& mask,
+                   std::vector<uint32_t>& off, std::vector<uint16_t>& pos)
+{
+    const int tx = (nx + 63) / 64, tyn = (ny + ty - 1) / ty;
+    off.assign((size_t)tx * tyn * nz + 1, 0);
+    pos.clear();
+    for (int by = 0; by < tyn; ++by)
+        for (int bx = 0; bx < tx; ++bx) {
+            const size_t c = (size_t)bx + (size_t)tx * by;
+            for (int z = 0; z < nz; ++z) {
+                off[c * nz + z] = (uint32_t)pos.size();
+                column_plane_order(nx, ny, bx * 64, by * ty, ty, [&](int x, int y) {
+                    const size_t n = ((size_t)z * ny + y) * nx + x;
+                    if (!mask[n]) pos.push_back((uint16_t)((x - bx * 64) + 64 * (y - by * ty)));
+                });
+            }
+        }
+    off.back() = (uint32_t)pos.size();
 }
 
 bool valid_params(const lbm_ms_params* p, std::string* why)
@@ -151,6 +200,12 @@ Layout layout(const lbm_ms_params& p)
     L.inst = take(2 * sizeof(StepArgs));
     L.tiles = take(L.tile_cap * 2 * sizeof(int4));
     L.ent = take(L.ent_cap * sizeof(uint32_t));
+    L.c3off = L.c3pos = 0;
+    if (compacted3d(p)) {
+        const size_t cols = (size_t)((p.nx + 63) / 64) * (size_t)((p.ny + 11) / 12);  // most at ty 12
+        L.c3off = take((cols * (size_t)p.nz + 1) * sizeof(uint32_t));
+        L.c3pos = take(N * sizeof(uint16_t));
+    }
     if (p.advection) {
         const size_t gb = (size_t)q * (size_t)plane_pitch((long long)N) * elem_bytes(p.precision);
         L.g[0] = take(gb);
@@ -190,6 +245,7 @@ struct lbm_ms_s {
     long long steps = 0, snap_step = 0;
     int ty = 0, cz = 0;
     int ntiles = 0;
+    int c3_ty = 0;  // tile height the 3D column lists in the workspace were built for (0: none)
     double* pinned = nullptr;
     std::string err;
 
@@ -297,7 +353,24 @@ struct lbm_ms_s {
 
     int upload_tiles()
     {
-        if (!is_2d(p.lattice) || !geom) return LBM_MS_OK;
+        if (!geom) return LBM_MS_OK;
+        if (!is_2d(p.lattice)) {
+            if (!compacted_ty(ty)) return LBM_MS_OK;
+            std::vector<uint32_t> off;
+            std::vector<uint16_t> pos;
+            build_cols_3d(p.nx, p.ny, p.nz, ty, mask, off, pos);
+            const size_t cap_off = (size_t)((p.nx + 63) / 64) * (size_t)((p.ny + 11) / 12) * p.nz + 1;
+            if (!compacted3d(p) || off.size() > cap_off || pos.size() != (size_t)n_fluid)
+                return fail(LBM_MS_E_ARG, "compacted column lists do not fit this handle");
+            int rc = hip(hipMemcpyAsync(ws + L.c3off, off.data(), off.size() * sizeof(uint32_t),
+                                        hipMemcpyHostToDevice, stream), "column list upload");
+            if (rc) return rc;
+            rc = hip(hipMemcpyAsync(ws + L.c3pos, pos.data(), pos.size() * sizeof(uint16_t),
+                                    hipMemcpyHostToDevice, stream), "column list upload");
+            if (rc) return rc;
+            c3_ty = ty;
+            return sync();
+        }
         std::vector<int4> tl;
         std::vector<uint32_t> en;
         build_tiles_2d(p.nx, p.ny, ty, cz, mask, 0, 0, tl, en);
@@ -388,13 +461,30 @@ long long clean_pores(const lbm_ms_params& p, std::vector<uint8_t>& solid)
     return open;
 }
 
-// Fluid nodes are numbered in raster order (x fastest); solid voxels map to -1.
-long long build_index(const std::vector<uint8_t>& solid, std::vector<int32_t>& idx)
+// Fluid nodes of a 2D box are numbered in raster order (x fastest).  A 3D box is numbered by
+// columns of 64 x 16 voxels (x-column fastest, then y), each column plane by plane: the nodes a
+// marching workgroup pulls in one plane then sit together in memory instead of sharing cache
+// lines with the columns beside it, which march out of step.  Within a column's plane come first
+// its two edge lines x = x0 and x = x0 + 63 (y increasing; the voxels a neighbouring column
+// reads as its side halo, now one short run each), then the rows between in raster order.
+// Solid voxels map to -1.
+long long build_index(const std::vector<uint8_t>& solid, int nx, int ny, int nz,
+                      std::vector<int32_t>& idx)
 {
     idx.assign(solid.size(), -1);
     long long k = 0;
-    for (size_t n = 0; n < solid.size(); ++n)
-        if (!solid[n]) idx[n] = (int32_t)k++;
+    if (nz == 1) {
+        for (size_t n = 0; n < solid.size(); ++n)
+            if (!solid[n]) idx[n] = (int32_t)k++;
+        return k;
+    }
+    for (int y0 = 0; y0 < ny; y0 += COL_Y)
+        for (int x0 = 0; x0 < nx; x0 += COL_X)
+            for (int z = 0; z < nz; ++z)
+                column_plane_order(nx, ny, x0, y0, COL_Y, [&](int x, int y) {
+                    const size_t n = ((size_t)z * ny + y) * nx + x;
+                    if (!solid[n]) idx[n] = (int32_t)k++;
+                });
     return k;
 }
 
@@ -524,6 +614,10 @@ int default_tile_y(const lbm_ms_params& p)
     // with 16-bit storage is built for four waves per SIMD: BF16 0.339 ms against 0.369 ms on
     // 256-lane tiles)
     if (p.lattice == LBM_MS_D3Q7) return 8;
+    // D3Q19 with global-shift 32- or 16-bit storage: the fluid-compacted 64 x 16 columns (FP32
+    // 0.754 ms against 0.886 ms for 64 x 8 voxels per workgroup, BF16 0.624 against 0.807);
+    // D3Q7 keeps 64 x 8 (0.368 ms against 0.396 ms compacted)
+    if (compacted3d(p)) return 16;
     return p.precision == LBM_MS_FP64 ? 4 : 8;
 }
 
@@ -541,6 +635,19 @@ int default_chunk_z(const lbm_ms_params& p)
         return (p.lattice == LBM_MS_D2Q5 && !node_shift(p)) ? 12 : 9;
     }
     if (p.chunk_z > 0) return p.chunk_z;
+    if (compacted_ty(default_tile_y(p))) {
+        // one workgroup per CU: the longest chunk (64, 32, 16 planes) that still gives every CU
+        // a workgroup (256^3 D3Q19 FP32 with 64 x 16 columns: 0.754 / 0.787 / 0.795 ms)
+        const int ty = default_tile_y(p);
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            const long long cols = (long long)((p.nx + 63) / 64) * ((p.ny + ty - 1) / ty);
+            for (int cz : {64, 32})
+                if (cols * ((p.nz + cz - 1) / cz) >= (long long)cus) return cz;
+        }
+        return ty == 16 ? 16 : 32;
+    }
     // Longer chunks spread each workgroup's prologue (five staged planes) over more planes, as
     // long as the grid still fills every resident workgroup slot: the largest of 128, 64 and 32
     // planes that does.  Measured on the 256^3 block with 512-lane tiles (32 -> 64 -> 128
@@ -562,10 +669,10 @@ int default_chunk_z(const lbm_ms_params& p)
     return p.nz >= 128 ? 32 : 16;
 }
 
-bool tile_ok(int lattice, int ty, int cz)
+bool tile_ok(int lattice, bool compacted, int ty, int cz)
 {
-    int tys[8], czs[8];
-    const int n = tile_options(lattice, tys, czs, 8);
+    int tys[16], czs[16];
+    const int n = tile_options(lattice, compacted, tys, czs, 16);
     for (int i = 0; i < n; ++i)
         if (tys[i] == ty && czs[i] == cz) return true;
     return false;
@@ -636,7 +743,7 @@ int lbm_ms_create(const lbm_ms_params* params, void* d_workspace, size_t bytes, 
     h->N = (long long)params->nx * params->ny * params->nz;
     h->ty = default_tile_y(*params);
     h->cz = default_chunk_z(*params);
-    if (!tile_ok(params->lattice, h->ty, h->cz)) {
+    if (!tile_ok(params->lattice, compacted3d(*params), h->ty, h->cz)) {
         delete h;
         return create_fail(LBM_MS_E_ARG, "tile shape not among lbm_ms_tile_options for this lattice");
     }
@@ -715,18 +822,18 @@ int lbm_ms_lattice_info(int lattice, int* q, int* e, double* w)
     return LBM_MS_OK;
 }
 
-int lbm_ms_tile_options(int lattice, int precision, int* tile_y, int* chunk_z, int cap)
+int lbm_ms_tile_options(int lattice, int precision, int shift_mode, int* tile_y, int* chunk_z, int cap)
 {
-    (void)precision;
     if (!known_lattice(lattice)) return LBM_MS_E_ARG;
-    return tile_options(lattice, tile_y, chunk_z, cap);
+    return tile_options(lattice, compacted3d(lattice, precision, shift_mode), tile_y, chunk_z, cap);
 }
 
 int lbm_ms_set_tile(lbm_ms_t h, int tile_y, int chunk_z)
 {
     if (!h) return LBM_MS_E_ARG;
-    if (!tile_ok(h->p.lattice, tile_y, chunk_z))
-        return h->fail(LBM_MS_E_ARG, "launch shape (%d, %d) not compiled", tile_y, chunk_z);
+    if (!tile_ok(h->p.lattice, compacted3d(h->p), tile_y, chunk_z))
+        return h->fail(LBM_MS_E_ARG, "launch shape (%d, %d) not compiled for this lattice and storage",
+                       tile_y, chunk_z);
     h->ty = tile_y;
     h->cz = chunk_z;
     int rc = h->upload_tiles();
@@ -750,7 +857,7 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
         for (long long n = h->p.nx - 1; n < h->N; n += h->p.nx) h->n_open += h->mask[n] ? 0 : 1;
     }
     std::vector<int32_t> idx;
-    h->n_fluid = build_index(h->mask, idx);
+    h->n_fluid = build_index(h->mask, h->p.nx, h->p.ny, h->p.nz, idx);
     h->P = plane_pitch(h->n_fluid);
     h->S[0] = h->S[1] = 0.0;  // a source layer belongs to the geometry it was set on
     h->src_x0 = 1 << 30;
@@ -801,7 +908,7 @@ int lbm_ms_work_list(int lattice, int nx, int ny, const uint8_t* solid, int tile
                      int64_t* n_tiles, int64_t* n_ent, int32_t* tiles, uint32_t* ent)
 {
     if (!solid || !n_tiles || !n_ent || nx < 2 || ny < 1) return LBM_MS_E_ARG;
-    if (!known_lattice(lattice) || !is_2d(lattice) || !tile_ok(lattice, tile_y, rows)) return LBM_MS_E_ARG;
+    if (!known_lattice(lattice) || !is_2d(lattice) || !tile_ok(lattice, false, tile_y, rows)) return LBM_MS_E_ARG;
     std::vector<uint8_t> m(solid, solid + (size_t)nx * ny);
     for (auto& v : m) v = v ? 1 : 0;
     std::vector<int4> tl;
@@ -969,7 +1076,11 @@ int lbm_ms_step(lbm_ms_t h, int64_t nsteps)
                               h->ns(), h->ty, h->cz);
         } else {
             StepArgs a = h->args(h->cur);
-            e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb);
+            const bool cols = compacted_ty(h->ty);
+            if (cols && h->c3_ty != h->ty) return h->fail(LBM_MS_E_STATE, "column lists not built");
+            e = launch_step(h->stream, a, h->p.lattice, h->prec(), h->ns(), h->ty, h->cz, nb,
+                            cols ? reinterpret_cast<const unsigned*>(h->ws + h->L.c3off) : nullptr,
+                            cols ? reinterpret_cast<const unsigned short*>(h->ws + h->L.c3pos) : nullptr);
         }
         if (e != hipSuccess) return h->hip(e, "step kernel");
         h->cur ^= 1;
@@ -1540,7 +1651,7 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     b->count = count;
     b->ty = default_tile_y(*common);
     b->rows = default_chunk_z(*common);
-    if (b->ty > 16 || !tile_ok(common->lattice, b->ty, b->rows)) {
+    if (b->ty > 16 || !tile_ok(common->lattice, false, b->ty, b->rows)) {
         b->ty = 8;
         b->rows = 0;
     }
@@ -1609,7 +1720,7 @@ int lbm_ms_batch_stats(lbm_ms_batch_t b, int* active, int64_t* fluid, int* tiles
 int lbm_ms_batch_set_tile(lbm_ms_batch_t b, int tile_y, int rows)
 {
     if (!b) return LBM_MS_E_ARG;
-    if (!tile_ok(b->common.lattice, tile_y, rows)) return b->fail(LBM_MS_E_ARG, "launch shape not compiled");
+    if (!tile_ok(b->common.lattice, false, tile_y, rows)) return b->fail(LBM_MS_E_ARG, "launch shape not compiled");
     int rc = b->enter();
     if (rc) return rc;
     b->ty = tile_y;

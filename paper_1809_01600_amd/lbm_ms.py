@@ -134,7 +134,7 @@ _SIGNATURES = [
     ("lbm_ms_get_info", ctypes.c_int, [_VP, ctypes.POINTER(lbm_ms_info)]),
     ("lbm_ms_lattice_info", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), _DP]),
-    ("lbm_ms_tile_options", ctypes.c_int, [ctypes.c_int, ctypes.c_int,
+    ("lbm_ms_tile_options", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     ("lbm_ms_set_tile", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
@@ -237,10 +237,13 @@ def work_list(lattice: str, solid: np.ndarray, tile_y: int, rows: int):
     return tiles, ent[:ne.value]
 
 
-def tile_options(lattice: int, precision: int = FP32):
+def tile_options(lattice: int, precision=FP32, shift_mode: int = SHIFT_GLOBAL):
+    """Compiled launch shapes (tile_y, chunk_z) for a lattice and storage mode."""
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
     ty = (ctypes.c_int * 16)()
     cz = (ctypes.c_int * 16)()
-    n = lib().lbm_ms_tile_options(lattice, precision, ty, cz, 16)
+    n = lib().lbm_ms_tile_options(lattice, precision, shift_mode, ty, cz, 16)
     return [(ty[i], cz[i]) for i in range(n)]
 
 

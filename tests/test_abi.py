@@ -80,6 +80,17 @@ def test_tile_options_and_status_strings():
     assert (16, 0) in lbm_ms.tile_options(lbm_ms.D2Q9)
     assert all(cz > 0 for _, cz in lbm_ms.tile_options(lbm_ms.D3Q19))
     assert lbm_ms.tile_options(lbm_ms.D3Q7) == lbm_ms.tile_options(lbm_ms.D3Q19)
+    # the fluid-compacted 3D columns (tile_y 12 and 16) exist for global-shift 32- and 16-bit
+    # storage only, and never in 2D
+    compacted = {(ty, cz) for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q19) if ty in (12, 16)}
+    assert (16, 32) in compacted and (12, 64) in compacted
+    for prec, shift in (("bf16", lbm_ms.SHIFT_GLOBAL), ("fp16", lbm_ms.SHIFT_GLOBAL)):
+        assert compacted <= set(lbm_ms.tile_options(lbm_ms.D3Q19, prec, shift))
+    for prec, shift in (("fp64", lbm_ms.SHIFT_GLOBAL), ("fp32", lbm_ms.SHIFT_NODE),
+                        ("bf16", lbm_ms.SHIFT_NODE)):
+        assert not compacted & set(lbm_ms.tile_options(lbm_ms.D3Q19, prec, shift))
+    assert all(ty <= 16 for ty, _ in lbm_ms.tile_options(lbm_ms.D2Q9))
+    assert len(lbm_ms.tile_options(lbm_ms.D2Q9)) == len(lbm_ms.tile_options(lbm_ms.D2Q9, "fp64"))
     for code in range(-9, 1):
         assert lbm_ms.lib().lbm_ms_status_string(code).decode() != "unknown status"
 

@@ -53,7 +53,7 @@ def test_porous_block_matches_oracle_on_every_launch_shape(mode, steps):
     o.step(steps)
     Xo = o.moments()
     fo, _, _, _ = o.collide()
-    for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q7):
+    for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q7, lbm_ms.FP64):
         s = lbm_ms.Solver(case, precision="fp64", tile_y=ty, chunk_z=cz, ms_mode=mode)
         assert np.array_equal(s.get_geometry(), o.solid)
         s.init()

@@ -105,7 +105,7 @@ def test_porous_2d_fp64_every_tile_shape(mode):
 def test_porous_3d_fp64_every_tile_shape():
     case = inputs.random_small(70, 20, 36, "D3Q19", seed=5, solid_frac=0.25, tau_ref=4.0)
     o = None
-    for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q19):
+    for ty, cz in lbm_ms.tile_options(lbm_ms.D3Q19, lbm_ms.FP64):
         s, o2 = _pair(case, tile_y=ty, chunk_z=cz)
         if o is None:
             o = o2
@@ -490,7 +490,7 @@ def test_3d_launch_shapes_in_every_storage_mode(lat, precision, shift, tol):
         o.step(30)
         _SHAPE_ORACLE[lat] = o.moments()
     Xo = _SHAPE_ORACLE[lat]
-    for ty, cz in lbm_ms.tile_options(lbm_ms.LATTICES[lat]):
+    for ty, cz in lbm_ms.tile_options(lbm_ms.LATTICES[lat], precision, shift):
         s = lbm_ms.Solver(case, precision=precision, shift_mode=shift, tile_y=ty, chunk_z=cz,
                           ms_mode=lbm_ms.STOICH)
         s.init()
@@ -499,3 +499,57 @@ def test_3d_launch_shapes_in_every_storage_mode(lat, precision, shift, tol):
         s.close()
         print("%s %s shift %d tile (%d, %d): max |dX| %.3e" % (lat, precision, shift, ty, cz, err))
         assert err <= tol, (ty, cz, err)
+
+
+COMPACTED = [(12, 32), (12, 64), (16, 16), (16, 32), (16, 64)]
+
+
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q7"])
+@pytest.mark.parametrize("shape,solid,steps", [((130, 17, 40), 0.05, 40), ((33, 3, 5), 0.15, 60),
+                                               ((70, 29, 37), 0.45, 40)],
+                         ids=["dense", "narrow", "porous"])
+def test_3d_compacted_columns_local_flux(lat, shape, solid, steps):
+    """The fluid-compacted 3D columns with the paper's local flux ratio (gradients enter tau), in
+    FP32 against the FP64 oracle and against the one-voxel-per-lane kernel: a nearly all-fluid
+    block (every plane of a column overflows its 512 lanes into a second pass), a box narrower
+    than a column with fewer planes than a chunk, and a porous block with ragged columns."""
+    nx, ny, nz = shape
+    seed = 21
+    while True:
+        case = inputs.random_small(nx, ny, nz, lat, seed=seed, solid_frac=solid, tau_ref=4.0)
+        if oracle.label(lat, case.mask())[1] > 0:
+            break
+        seed += 1
+    o = oracle.Oracle(case)
+    o.init_uniform()
+    o.step(steps)
+    Xo = o.moments()
+    ref = lbm_ms.Solver(case, precision="fp32", tile_y=8, chunk_z=32)
+    ref.init()
+    ref.step(steps)
+    Xr = ref.get_fields()
+    ref.close()
+    err_ref = float(np.max(np.abs(Xr - Xo)))
+    print("%s %s: one voxel per lane, max |dX| vs oracle %.3e" % (lat, shape, err_ref))
+    assert err_ref <= 2e-6
+    for ty, cz in COMPACTED:
+        s = lbm_ms.Solver(case, precision="fp32", tile_y=ty, chunk_z=cz)
+        s.init()
+        s.step(steps)
+        X = s.get_fields()
+        s.close()
+        err = float(np.max(np.abs(X - Xo)))
+        d = float(np.max(np.abs(X - Xr)))
+        print("  tile (%d, %d): max |dX| vs oracle %.3e, vs one voxel per lane %.3e" % (ty, cz, err, d))
+        assert err <= 2e-6 and d <= 1e-6, (ty, cz, err, d)
+
+
+def test_3d_compacted_columns_rejected_where_not_built():
+    case = inputs.random_small(20, 9, 7, "D3Q19", seed=5, solid_frac=0.2, tau_ref=4.0)
+    for kw in (dict(precision="fp64"), dict(precision="fp32", shift_mode=lbm_ms.SHIFT_NODE)):
+        with pytest.raises(lbm_ms.LbmMsError):
+            lbm_ms.Solver(case, tile_y=16, chunk_z=32, **kw)
+        s = lbm_ms.Solver(case, tile_y=8, chunk_z=32, **kw)
+        with pytest.raises(lbm_ms.LbmMsError):
+            s.set_tile(12, 32)
+        s.close()
