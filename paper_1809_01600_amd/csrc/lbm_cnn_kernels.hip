@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "lbm_cnn.h"
 
@@ -365,12 +366,103 @@ inline int grid_for(long long n, int bs = 256, int cap = 8192)
 
 inline int status(hipError_t e) { return e == hipSuccess ? 0 : -4; }
 
+// BF16 convolution on the matrix cores: 32 output channels from CIN = 8 or 32 input channels, as
+// the implicit GEMM out[pixel][co] = sum_kk A[pixel][kk] W[kk][co] with kk = tap * CIN + ci (taps
+// 0..8 row-major over the 3x3 window), in K chunks of 32 by v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation).  One workgroup = one 16x16 pixel tile of one image, four waves; wave v owns tile
+// rows 4v..4v+3 (one 16-pixel M block each) and both 16-channel N blocks.  LDS holds the 18x18
+// input tile pixel-major (the CIN channels of a pixel together) and the weights as [tap][co][ci],
+// so each lane's eight K values of an operand are one 16-byte read: A lane l takes pixel l % 16
+// of its row and kk = 32 m + 8 (l / 16) .. + 7, B lane l takes channel l % 16 of its block and the
+// same kk; D lane l holds rows (pixels) 4 (l / 16) + j, j = 0..3, of channel l % 16.  A K chunk
+// past tap 8 (CIN = 8: 72 = 9 x 8 kk padded to 96) reads zeros.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv_fwd_mfma(const uint16_t* __restrict__ in, int H, int W,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, int relu,
+                                                       uint16_t* __restrict__ out)
+{
+    constexpr int COUT = 32, KCH = (9 * CIN + 31) / 32;  // K chunks of 32
+    __shared__ __align__(16) uint16_t sIn[HALO * HALO * CIN];
+    __shared__ __align__(16) uint16_t sW[(KCH * 32 / CIN) * COUT * CIN];  // taps padded to the chunks
+    const int b = blockIdx.z;
+    const long long plane = (long long)H * W;
+    const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
+    // stage: weights w[co][ci][tap] -> sW[tap][co][ci] (padding taps zero), inputs NCHW -> [pix][ci]
+    for (int i = threadIdx.x; i < (KCH * 32 / CIN) * COUT * CIN; i += 256) {
+        const int ci = i % CIN, co = (i / CIN) % COUT, tap = i / (CIN * COUT);
+        sW[i] = tap < 9 ? w[(co * CIN + ci) * 9 + tap] : (uint16_t)0;
+    }
+    for (int i = threadIdx.x; i < CIN * HALO * HALO; i += 256) {
+        const int c = i / (HALO * HALO), r = i % (HALO * HALO);
+        const int gy = ty0 + r / HALO - 1, gx = tx0 + r % HALO - 1;
+        uint16_t v = 0;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = in[((long long)b * CIN + c) * plane + (long long)gy * W + gx];
+        sIn[r * CIN + c] = v;
+    }
+    __syncthreads();
+    const int l = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const int lr = l & 15, lg = l >> 4;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KCH; ++kc) {
+        const int kk = kc * 32 + lg * 8;  // this lane group's first K index
+        const int tap = kk / CIN, ci0 = kk % CIN;
+        const int ky = tap < 9 ? tap / 3 : 0, kx = tap < 9 ? tap % 3 : 0;
+        bf16x8 bw[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+            bw[n] = *reinterpret_cast<const bf16x8*>(&sW[(tap * COUT + n * 16 + lr) * CIN + ci0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int py = 4 * v + m;  // tile row of this M block; pixel x = lr
+            bf16x8 a = *reinterpret_cast<const bf16x8*>(&sIn[((py + ky) * HALO + lr + kx) * CIN + ci0]);
+            if (tap >= 9) a = bf16x8{};  // padded K: zero operand
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[n], acc[m][n], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int y = ty0 + 4 * v + m;
+        if (y >= H) continue;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int co = n * 16 + lr;
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = tx0 + 4 * lg + j;
+                float o = acc[m][n][j] + bb;
+                if (relu) o = o > 0.f ? o : 0.f;
+                if (x < W) out[((long long)b * COUT + co) * plane + (long long)y * W + x] = f32_to_bf16(o);
+            }
+        }
+    }
+}
+
 template <class T, class WT>
 int conv_forward(const T* in, const float* gate, int B, int Cin, int H, int W, const WT* w,
                  const float* b, int Cout, int relu, T* out, hipStream_t st)
 {
     if (!in || !w || !out || B <= 0 || H <= 0 || W <= 0 || Cin <= 0 || Cin > MAXC) return -1;
     const dim3 grid((W + TS - 1) / TS, (H + TS - 1) / TS, B);
+    if constexpr (std::is_same<T, uint16_t>::value && std::is_same<WT, uint16_t>::value) {
+        // BF16 inference: the 32-channel layers on the matrix cores
+        if (Cout == 32 && !gate && (Cin == 8 || Cin == 32)) {
+            if (Cin == 8) hipLaunchKernelGGL((k_conv_fwd_mfma<8>), grid, dim3(256), 0, st, in, H, W, w, b, relu, out);
+            else hipLaunchKernelGGL((k_conv_fwd_mfma<32>), grid, dim3(256), 0, st, in, H, W, w, b, relu, out);
+            return status(hipGetLastError());
+        }
+    }
     switch (Cout) {
     case 32: hipLaunchKernelGGL((k_conv_fwd<T, WT, 32>), grid, dim3(TS * TS), 0, st, in, gate, Cin, H, W, w, b, relu, out); break;
     case 8: hipLaunchKernelGGL((k_conv_fwd<T, WT, 8>), grid, dim3(TS * TS), 0, st, in, gate, Cin, H, W, w, b, relu, out); break;

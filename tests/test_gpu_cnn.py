@@ -75,6 +75,40 @@ def test_bf16_inference_against_the_fp64_reference():
     assert np.max(np.abs(p32 - r)) <= 2e-5 * np.max(np.abs(r))
 
 
+@pytest.mark.parametrize("cin", [8, 32])
+@pytest.mark.parametrize("relu", [0, 1])
+def test_bf16_layer_on_the_matrix_cores(cin, relu):
+    """One 32-output-channel BF16 layer (the matrix-core path) against the FP64 convolution of the
+    same BF16-rounded inputs and weights: the FP32 accumulation of at most 288 products is exact
+    to about 1e-6 relative, so each output must be the FP64 value rounded to BF16 (relative 2^-8)
+    up to that.  Ragged 16x16 tiles (21 x 37) and two images."""
+    B, H, W, cout = 2, 21, 37, 32
+    rng = np.random.default_rng(11 + cin + relu)
+    x = torch.tensor(rng.normal(size=(B, cin, H, W)), dtype=torch.bfloat16, device="cuda")
+    w = torch.tensor(rng.normal(size=(cout, cin, 3, 3)) / np.sqrt(9 * cin), dtype=torch.bfloat16,
+                     device="cuda")
+    b = torch.tensor(rng.normal(size=cout) * 0.1, dtype=torch.float32, device="cuda")
+    out = torch.empty((B, cout, H, W), dtype=torch.bfloat16, device="cuda")
+    p = lambda t: t.data_ptr()  # noqa: E731
+    rc = cnn.lib().lbm_cnn_conv_forward_bf16(p(x), B, cin, H, W, p(w), p(b), cout, relu, p(out),
+                                             torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    got = out.float().cpu().double().numpy()
+    xd = x.float().cpu().double().numpy()
+    wd = w.float().cpu().double().numpy()
+    xp = np.pad(xd, ((0, 0), (0, 0), (1, 1), (1, 1)))
+    r = np.zeros((B, cout, H, W)) + b.cpu().double().numpy()[None, :, None, None]
+    for ky in range(3):
+        for kx in range(3):
+            r += np.einsum("oc,bchw->bohw", wd[:, :, ky, kx], xp[:, :, ky:ky + H, kx:kx + W])
+    if relu:
+        r = np.maximum(r, 0.0)
+    scale = np.max(np.abs(r))
+    err = np.abs(got - r)
+    print("cin %d relu %d: max |out - ref| %.3e, max |ref| %.3e" % (cin, relu, err.max(), scale))
+    assert np.all(err <= 2.0 ** -8 * np.abs(r) + 1e-5 * scale)
+
+
 def test_training_reduces_loss():
     net, feat, target, fluid = _net_and_data(B=4, H=32, W=32, seed=7)
     ft, tt, fl = (torch.tensor(a, device="cuda") for a in (feat, target * 0.1, fluid))
