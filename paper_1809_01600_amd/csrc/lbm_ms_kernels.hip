@@ -88,15 +88,19 @@ struct PlaneRegs {
 template <int RX, int RY, int NT>
 __device__ inline void stage_issue(const StepArgs& a, int x0, int y0, int z, PlaneRegs<RX, RY, NT>& r)
 {
-    const long long zb = (long long)((z % a.nz + a.nz) % a.nz) * a.nx * a.ny;
+    // the box and the map read once, before the loads (read inside the conditional loads they
+    // would be fetched again, with a wait, for every element)
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int* idx = a.idx;
+    const long long zb = (long long)((z % nz + nz) % nz) * nx * ny;
 #pragma unroll
     for (int j = 0; j < (RX * RY + NT - 1) / NT; ++j) {
         const int t = threadIdx.x + j * NT;
         const int rx = t % RX, ry = t / RX;
         const int gx = x0 - 2 + rx;
-        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
-        r.v[j] = (t < RX * RY && gx >= 0 && gx < a.nx)
-                     ? gload<int>(a.idx, (unsigned)(zb + (long long)gy * a.nx + gx) * 4u) : -2;
+        const int gy = wrap_row<RY>(y0 - 2 + ry, ny);
+        r.v[j] = (t < RX * RY && gx >= 0 && gx < nx)
+                     ? gload<int>(idx, (unsigned)(zb + (long long)gy * nx + gx) * 4u) : -2;
     }
 }
 template <int RX, int RY, int NT>
@@ -109,19 +113,68 @@ __device__ inline void stage_store(const PlaneRegs<RX, RY, NT>& r, int* dst)
     }
 }
 
-// stage_plane plus, for the NODE shift, the FP64 references c of every staged fluid node
-// (loaded by the same thread right after its index, so one barrier covers both).
-template <int RX, int RY>
-__device__ inline void stage_plane_refs(const StepArgs& a, int x0, int y0, int* dst, double* sc)
+// The index maps of planes z0 - 2 .. z0 + 2 into ring slots (zr + 2) % NPL, every load issued
+// before the first store (a loop of load, wait and store per element would take one memory round
+// trip per element a thread stages).
+template <int RX, int RY, int NT, int NPL>
+__device__ inline void stage_ring(const StepArgs& a, int x0, int y0, int z0, int* sI)
 {
-    for (int t = threadIdx.x; t < RX * RY; t += blockDim.x) {
-        const int rx = t % RX, ry = t / RX;
-        const int gx = x0 - 2 + rx;
-        const int gy = wrap_row<RY>(y0 - 2 + ry, a.ny);
-        const int i = (gx >= 0 && gx < a.nx) ? gload<int>(a.idx, (unsigned)((long long)gy * a.nx + gx) * 4u) : -2;
-        dst[t] = i;
-        sc[t] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
-        sc[RX * RY + t] = i >= 0 ? gload<double>(a.xin, (unsigned)(a.NF + i) * 8u) : 0.0;
+    PlaneRegs<RX, RY, NT> r[5];
+#pragma unroll
+    for (int zr = -2; zr <= 2; ++zr) stage_issue<RX, RY, NT>(a, x0, y0, z0 + zr, r[zr + 2]);
+#pragma unroll
+    for (int zr = -2; zr <= 2; ++zr) stage_store<RX, RY, NT>(r[zr + 2], sI + ((zr + 2) % NPL) * RY * RX);
+}
+
+// The second half of staging a plane for the NODE shift, once stage_issue's index loads are in
+// registers: the FP64 references c of its fluid nodes (all loads issued first), then the index
+// map into dst and the references into sc ([species][RY * RX]).
+template <int RX, int RY, int NT>
+__device__ inline void stage_refs_store(const StepArgs& a, const PlaneRegs<RX, RY, NT>& r, int* dst,
+                                        double* sc)
+{
+    constexpr int NR = (RX * RY + NT - 1) / NT;
+    double c0[NR], c1[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int i = r.v[j];
+        c0[j] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
+        c1[j] = i >= 0 ? gload<double>(a.xin, (unsigned)(a.NF + i) * 8u) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int t = threadIdx.x + j * NT;
+        if (t < RX * RY) {
+            dst[t] = r.v[j];
+            sc[t] = c0[j];
+            sc[RX * RY + t] = c1[j];
+        }
+    }
+}
+
+// stage_plane of a 2D box plus, for the NODE shift, the FP64 references c of every staged fluid
+// node, in three rounds: all index loads, then all reference loads, then the stores (NT threads).
+template <int RX, int RY, int NT>
+__device__ inline void stage_plane_refs_pipelined(const StepArgs& a, int x0, int y0, int* dst, double* sc)
+{
+    constexpr int NR = (RX * RY + NT - 1) / NT;
+    PlaneRegs<RX, RY, NT> r;
+    stage_issue<RX, RY, NT>(a, x0, y0, 0, r);
+    double c0[NR], c1[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int i = r.v[j];
+        c0[j] = i >= 0 ? gload<double>(a.xin, (unsigned)i * 8u) : 0.0;
+        c1[j] = i >= 0 ? gload<double>(a.xin, (unsigned)(a.NF + i) * 8u) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int t = threadIdx.x + j * NT;
+        if (t < RX * RY) {
+            dst[t] = r.v[j];
+            sc[t] = c0[j];
+            sc[RX * RY + t] = c1[j];
+        }
     }
 }
 
@@ -260,8 +313,12 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
     const unsigned dummy = (1u << 8) | 1u;
     const unsigned pe0 = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
     const unsigned pe2 = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
+    // Global-shift storage stages the map one element at a time (a load and its store per
+    // iteration): issuing all of a thread's loads first was 3% slower on the 64-slice batch (528
+    // against 511 us; the 1024^2 slice gained 2%).  The NODE shift, whose references need the
+    // indices first, issues each round of loads together (the 1024^2 slice: 21.2 against 23.2 us).
     if constexpr (NS)
-        stage_plane_refs<RX, RY>(a, x0, y0, sI, sC);
+        stage_plane_refs_pipelined<RX, RY, BS>(a, x0, y0, sI, sC);
     else
         stage_plane<RX, RY>(a, x0, y0, 0, sI);
     __syncthreads();
@@ -352,8 +409,12 @@ __global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k
     };
 
     // planes z0-2 .. z0+2 (relative -2 .. 2) into the ring
-    for (int zr = -2; zr <= 2; ++zr)
-        stage(zr);
+    if constexpr (NS) {
+        for (int zr = -2; zr <= 2; ++zr)
+            stage(zr);
+    } else {
+        stage_ring<RX, RY, 64 * TY, NPL>(a, x0, y0, z0, sI);
+    }
     __syncthreads();
 
     // plane z0-1: moments only (z gradient of plane z0); plane z0: populations and moments
@@ -393,12 +454,13 @@ __global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k
     }
     __syncthreads();  // the ring slot of plane z0-2 is free from here on
 
-    // Global-shift storage overlaps the memory round trips of an iteration: the index loads of the
-    // plane staged for later and the population loads of the own column and of the halo are all
-    // issued before any of them is used, and the staged plane is stored to LDS last (its slot is
-    // not read in this iteration, but the compiler cannot tell, so an early store would hold the
-    // pull's LDS reads behind the index loads).  FP64 keeps the halo after the own column: its
-    // registers are already full.
+    // The memory round trips of an iteration overlap: the index loads of the plane staged for
+    // later and the population loads of the own column and of the halo are all issued before any
+    // of them is used, and the staged plane is stored to LDS last (its slot is not read in this
+    // iteration, but the compiler cannot tell, so an early store would hold the pull's LDS reads
+    // behind the index loads).  The NODE shift then loads the staged plane's references, which
+    // need the indices, in one more round trip before the store.  FP64 keeps the halo after the
+    // own column: its registers are already full.
     constexpr bool OVERLAP = !NS;
     constexpr bool MERGE_HALO = !NS && P != P_F64;
     // The in-plane half of the Maxwell-Stefan work (x/y gradients, [B], 1/det) can run while the
@@ -411,11 +473,9 @@ __global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k
         const int zi = z0 + it;
         if (zi >= a.nz) break;  // uniform across the workgroup
         // stage plane it+3 (read by the next iteration's pull)
+        // (the NODE shift also needs the plane's references, loaded once the indices are in)
         PlaneRegs<RX, RY, 64 * TY> stg;
-        if constexpr (OVERLAP)
-            stage_issue<RX, RY, 64 * TY>(a, x0, y0, z0 + it + 3, stg);
-        else
-            stage(it + 3);
+        stage_issue<RX, RY, 64 * TY>(a, x0, y0, z0 + it + 3, stg);
         // pull plane it+1: own column (populations kept) and, if the next plane is output, its halo
         const int zr = it + 1;
         const int pslot = (zr + 2) % NPL;
@@ -477,7 +537,11 @@ __global__ __launch_bounds__(64 * TY, (step3d_min_waves<L, P, NS, TY>())) void k
                 sX[s_next][1][hy + 1][hx + 1] = h1;
             }
         }
-        if constexpr (OVERLAP) stage_store<RX, RY, 64 * TY>(stg, sI + (it + 5) % NPL * RY * RX);
+        if constexpr (OVERLAP)
+            stage_store<RX, RY, 64 * TY>(stg, sI + (it + 5) % NPL * RY * RX);
+        else
+            stage_refs_store<RX, RY, 64 * TY>(a, stg, sI + (it + 5) % NPL * RY * RX,
+                                              sC + (it + 5) % NPL * 2 * RY * RX);
         __syncthreads();
         if (own && ic >= 0) {
             const bool zpf = nbc & NB_ZP, zmf = nbc & NB_ZM;
@@ -599,7 +663,7 @@ __global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* 
         if (hit) gstore<unsigned>(a.flags, 0u, 1u);
     };
 
-    for (int zr = -2; zr <= 2; ++zr) stage_plane<RX, RY>(a, x0, y0, z0 + zr, sI + ((zr + 2) % NPL) * RY * RX);
+    stage_ring<RX, RY, NT, NPL>(a, x0, y0, z0, sI);
     __syncthreads();
 
     // plane z0-1: moments of every fluid voxel (z gradients of plane z0)
