@@ -153,8 +153,9 @@ __global__ __launch_bounds__(256) void k_adv_step(StepArgs a, AdvArgs v)
     using CT = typename C::CT;
     using raw = typename C::raw;
     constexpr unsigned ES = sizeof(raw);
-    const unsigned plane = (unsigned)a.P * ES;
-    const unsigned spec = (unsigned)L::Q * plane;
+    const unsigned plane = (unsigned)a.P * ES;             // velocity model: [Q][P]
+    const unsigned link = pop_link<ES>(a);                   // species: the population layout
+    const unsigned spec = pop_spec<L, ES>(a);
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < a.N;
          n += (long long)gridDim.x * blockDim.x) {
         const int i = a.idx[n];
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(256) void k_adv_step(StepArgs a, AdvArgs v)
         const CT o0 = (CT)om0, o1 = (CT)om1, of = (CT)v.om_flow;
         const CT x0 = (CT)X0, x1 = (CT)X1, r = (CT)rho;
         const unsigned base = (unsigned)i * ES;
+        const unsigned sbase = pop_node<ES>((unsigned)i);
 #pragma unroll
         for (int k = 0; k < L::Q; ++k) {
             const CT wk = wgt<L, CT>(k);
@@ -217,10 +219,10 @@ __global__ __launch_bounds__(256) void k_adv_step(StepArgs a, AdvArgs v)
             const CT s0 = f[0][k] + o0 * (wk * x0 * ((CT)1 + em) - f[0][k]);
             const CT s1 = f[1][k] + o1 * (wk * x1 * ((CT)1 + em) - f[1][k]);
             const CT gg = g[k] + of * (wk * (r + eu) - g[k]);
-            const unsigned off = base + (unsigned)k * plane;
+            const unsigned off = sbase + (unsigned)k * link;
             gstore<raw>(a.fout, off, C::enc(s0, CT(0)));
             gstore<raw>(a.fout, off + spec, C::enc(s1, CT(0)));
-            gstore<raw>(v.gout, off, C::enc(gg, CT(0)));
+            gstore<raw>(v.gout, base + (unsigned)k * plane, C::enc(gg, CT(0)));
         }
     }
 }

@@ -225,6 +225,36 @@ struct StepArgs {
     double trt_lambda;        // (tau_even - 1/2)(tau - 1/2)
 };
 
+// Population layout: the two evolved species of one (link, node) pair side by side,
+// [link][node][species] (P nodes per link), so that one 2-element load or store moves both: a
+// pull issues Q memory instructions per node instead of 2Q.  pop_node: byte offset of node m in
+// link 0; pop_link: bytes between links; pop_spec: bytes between the two species of a pair.
+// With LBMMS_SOA the plain layout [species][link][P] is used instead.
+#ifdef LBMMS_SOA
+template <unsigned ES>
+__device__ inline unsigned pop_node(unsigned m) { return m * ES; }
+template <unsigned ES>
+__device__ inline unsigned pop_link(const StepArgs& a) { return (unsigned)a.P * ES; }
+template <class L, unsigned ES>
+__device__ inline unsigned pop_spec(const StepArgs& a) { return (unsigned)L::Q * (unsigned)a.P * ES; }
+template <class L>
+__device__ inline long long pop_elem(const StepArgs& a, int j, long long i) { return (long long)j * a.P + i; }
+#else
+template <unsigned ES>
+__device__ inline unsigned pop_node(unsigned m) { return m * (2u * ES); }
+template <unsigned ES>
+__device__ inline unsigned pop_link(const StepArgs& a) { return (unsigned)a.P * (2u * ES); }
+template <class L, unsigned ES>
+__device__ inline unsigned pop_spec(const StepArgs& a) { (void)a; return ES; }
+// element index of population j = s Q + k (species s, link k) of node i
+template <class L>
+__device__ inline long long pop_elem(const StepArgs& a, int j, long long i)
+{
+    const int s = j >= L::Q ? 1 : 0;
+    return ((long long)(j - s * L::Q) * a.P + i) * 2 + s;
+}
+#endif
+
 // Map the hardware block index to a tile so that each of the 8 XCDs (blocks are dealt to XCDs
 // round-robin) works on one contiguous band of tiles and shares halo rows through its own L2.
 __device__ inline int xcd_tile(int b, int nb)
@@ -343,8 +373,8 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
     using raw = typename C::raw;
     constexpr unsigned ES = sizeof(raw);
     const void* fin = a.fin;
-    const unsigned plane = (unsigned)a.P * ES;
-    const unsigned spec = (unsigned)L::Q * plane;
+    const unsigned plane = pop_link<ES>(a);
+    const unsigned spec = pop_spec<L, ES>(a);
     const double co0 = ref.own(0, i);
     const double co1 = ref.own(1, i);
     const bool wall = a.inlet_wall != 0;
@@ -358,7 +388,7 @@ __device__ inline void gather_ns(const StepArgs& a, int i, const int (&si)[L::Q]
         const bool local = (s < 0) || from_out || from_in;
         const bool reflect = (s == -1) || from_out || (from_in && wall);
         const unsigned m = (unsigned)(local ? i : s);
-        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + m * ES;
+        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + pop_node<ES>(m);
         g[0][k] = C::dec(gload<raw>(fin, off), 0.f);
         g[1][k] = C::dec(gload<raw>(fin, off + spec), 0.f);
         dc[0][k] = local ? 0.f : (float)(ref.template src<L>(0, k, m) - co0);
@@ -414,8 +444,8 @@ __device__ inline void gather_issue(const StepArgs& a, int i, const int (&si)[L:
     using raw = typename Codec<P>::raw;
     constexpr unsigned ES = sizeof(raw);
     const void* fin = a.fin;
-    const unsigned plane = (unsigned)a.P * ES;          // bytes per (species, link) plane
-    const unsigned spec = (unsigned)L::Q * plane;       // bytes per species
+    const unsigned plane = pop_link<ES>(a);             // bytes between links
+    const unsigned spec = pop_spec<L, ES>(a);           // ... and between the two species
     const bool wall = a.inlet_wall != 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -426,7 +456,7 @@ __device__ inline void gather_issue(const StepArgs& a, int i, const int (&si)[L:
         const bool local = (s < 0) || from_out || from_in;  // read this node's own entry
         const bool reflect = (s == -1) || from_out || (from_in && wall);
         const unsigned m = (unsigned)(local ? i : s);
-        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + m * ES;
+        const unsigned off = (reflect ? (unsigned)L::opp[k] : (unsigned)k) * plane + pop_node<ES>(m);
         r[0][k] = gload<raw>(fin, off);
         r[1][k] = gload<raw>(fin, off + spec);
     }
@@ -633,9 +663,9 @@ __device__ inline void collide_store(const StepArgs& a, int n,
     using raw = typename C::raw;
     constexpr unsigned ES = sizeof(raw);
     void* fout = a.fout;
-    const unsigned plane = (unsigned)a.P * ES;
-    const unsigned spec = (unsigned)L::Q * plane;
-    const unsigned base = (unsigned)n * ES;
+    const unsigned plane = pop_link<ES>(a);
+    const unsigned spec = pop_spec<L, ES>(a);
+    const unsigned base = pop_node<ES>((unsigned)n);
     // TRT: the odd part of a link pair relaxes with omega (it carries the flux, so Eq. 25 still
     // sets D); the even part with omega_e = 1 / (1/2 + Lambda / (1/omega - 1/2))
     double oe0 = om0, oe1 = om1;

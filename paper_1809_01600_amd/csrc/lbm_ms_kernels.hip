@@ -824,8 +824,8 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
             a.xout[a.NF + i] = v1;
 #pragma unroll
             for (int k = 0; k < L::Q; ++k) {
-                fout[(long long)k * a.P + i] = C::enc(0.f, 0.f);
-                fout[(long long)(L::Q + k) * a.P + i] = C::enc(0.f, 0.f);
+                fout[pop_elem<L>(a, k, i)] = C::enc(0.f, 0.f);
+                fout[pop_elem<L>(a, L::Q + k, i)] = C::enc(0.f, 0.f);
             }
             continue;
         }
@@ -836,11 +836,11 @@ __global__ void k_init(StepArgs a, const double* X, double u0, double u1)
             const CT e0 = wgt<L, CT>(k) * (CT)v0, e1 = wgt<L, CT>(k) * (CT)v1;
             if constexpr (C::shifted) {
                 const float wf = L::wf[k];
-                fout[(long long)k * a.P + i] = C::enc(e0, wf * c0);
-                fout[(long long)(L::Q + k) * a.P + i] = C::enc(e1, wf * c1);
+                fout[pop_elem<L>(a, k, i)] = C::enc(e0, wf * c0);
+                fout[pop_elem<L>(a, L::Q + k, i)] = C::enc(e1, wf * c1);
             } else {
-                fout[(long long)k * a.P + i] = C::enc(e0, CT(0));
-                fout[(long long)(L::Q + k) * a.P + i] = C::enc(e1, CT(0));
+                fout[pop_elem<L>(a, k, i)] = C::enc(e0, CT(0));
+                fout[pop_elem<L>(a, L::Q + k, i)] = C::enc(e1, CT(0));
             }
         }
     }
@@ -862,15 +862,15 @@ __device__ inline void node_moments(const StepArgs& a, int i, double& X0, double
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         if constexpr (NS) {
-            s0 += (double)C::dec(fin[(long long)k * a.P + i], 0.f);
-            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], 0.f);
+            s0 += (double)C::dec(fin[pop_elem<L>(a, k, i)], 0.f);
+            s1 += (double)C::dec(fin[pop_elem<L>(a, L::Q + k, i)], 0.f);
         } else if constexpr (C::shifted) {
             const float wf = L::wf[k];
-            s0 += (double)C::dec(fin[(long long)k * a.P + i], wf * c0);
-            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], wf * c1);
+            s0 += (double)C::dec(fin[pop_elem<L>(a, k, i)], wf * c0);
+            s1 += (double)C::dec(fin[pop_elem<L>(a, L::Q + k, i)], wf * c1);
         } else {
-            s0 += (double)C::dec(fin[(long long)k * a.P + i], 0);
-            s1 += (double)C::dec(fin[(long long)(L::Q + k) * a.P + i], 0);
+            s0 += (double)C::dec(fin[pop_elem<L>(a, k, i)], 0);
+            s1 += (double)C::dec(fin[pop_elem<L>(a, L::Q + k, i)], 0);
         }
     }
     X0 = s0;
@@ -980,16 +980,16 @@ __global__ __launch_bounds__(256) void k_faces(StepArgs a, double* partial)
                 // post-collision population of this node leaving through the face
                 double o0, o1;
                 if constexpr (NS) {
-                    o0 = L::w[q] * a.xin[i] + (double)C::dec(fin[(long long)q * a.P + i], 0.f);
+                    o0 = L::w[q] * a.xin[i] + (double)C::dec(fin[pop_elem<L>(a, q, i)], 0.f);
                     o1 = L::w[q] * a.xin[a.NF + i] +
-                         (double)C::dec(fin[(long long)(L::Q + q) * a.P + i], 0.f);
+                         (double)C::dec(fin[pop_elem<L>(a, L::Q + q, i)], 0.f);
                 } else if constexpr (C::shifted) {
                     const float wf = L::wf[q];
-                    o0 = C::dec(fin[(long long)q * a.P + i], wf * c0);
-                    o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], wf * c1);
+                    o0 = C::dec(fin[pop_elem<L>(a, q, i)], wf * c0);
+                    o1 = C::dec(fin[pop_elem<L>(a, L::Q + q, i)], wf * c1);
                 } else {
-                    o0 = C::dec(fin[(long long)q * a.P + i], 0);
-                    o1 = C::dec(fin[(long long)(L::Q + q) * a.P + i], 0);
+                    o0 = C::dec(fin[pop_elem<L>(a, q, i)], 0);
+                    o1 = C::dec(fin[pop_elem<L>(a, L::Q + q, i)], 0);
                 }
                 if (side == 0) {
                     if (L::ex[q] == 1) { cross0 += p0; cross1 += p1; }
@@ -1055,7 +1055,7 @@ __global__ void k_populations(StepArgs a, int s, int q, double* out)
         const int i = a.idx[n];
         if (i >= 0) {
             const float c = (float)(s ? a.c1 : a.c0);
-            const raw r = fin[((long long)s * L::Q + q) * a.P + i];
+            const raw r = fin[pop_elem<L>(a, s * L::Q + q, i)];
             if constexpr (NS) v = L::w[q] * a.xin[(long long)s * a.NF + i] + (double)C::dec(r, 0.f);
             else if constexpr (C::shifted) v = C::dec(r, L::wf[q] * c);
             else v = C::dec(r, 0);

@@ -23,7 +23,7 @@ namespace {
 constexpr double R_GAS = 8.3145;    // J / (mol K)
 constexpr double FARADAY = 96485.0; // C / mol (Eq. 39)
 constexpr int RED_BLOCKS = 1024;    // per-block partials of the reductions
-constexpr uint64_t STATE_MAGIC = 0x324d534c42304c31ull;
+constexpr uint64_t STATE_MAGIC = 0x334d534c42304c31ull;
 
 struct Layout {
     size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
