@@ -313,14 +313,16 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
     const unsigned dummy = (1u << 8) | 1u;
     const unsigned pe0 = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
     const unsigned pe2 = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
-    // Global-shift storage stages the map one element at a time (a load and its store per
-    // iteration): issuing all of a thread's loads first was 3% slower on the 64-slice batch (528
-    // against 511 us; the 1024^2 slice gained 2%).  The NODE shift, whose references need the
-    // indices first, issues each round of loads together (the 1024^2 slice: 21.2 against 23.2 us).
-    if constexpr (NS)
+    // Every staging load of a thread is issued before its first store (a loop of load, wait and
+    // store per element costs a memory round trip per element); the NODE shift's references,
+    // which need the indices, follow in a second round.
+    if constexpr (NS) {
         stage_plane_refs_pipelined<RX, RY, BS>(a, x0, y0, sI, sC);
-    else
-        stage_plane<RX, RY>(a, x0, y0, 0, sI);
+    } else {
+        PlaneRegs<RX, RY, BS> stg;
+        stage_issue<RX, RY, BS>(a, x0, y0, 0, stg);
+        stage_store<RX, RY, BS>(stg, sI);
+    }
     __syncthreads();
 
     // Tiles whose nodes and halo touch neither the inlet column nor the outlet column run a copy
