@@ -1202,6 +1202,8 @@ static hipError_t launch_step2d_p(hipStream_t st, const StepArgs* insts, const i
         hipLaunchKernelGGL((k_step2d<L, P, NS, 16, 16>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent);
     else if (ty == 8 && rows == 12)
         hipLaunchKernelGGL((k_step2d<L, P, NS, 8, 12>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent);
+    else if (ty == 16 && rows == 24)
+        hipLaunchKernelGGL((k_step2d<L, P, NS, 16, 24>), dim3(ntiles), dim3(32 * 16), 0, st, insts, tiles, ent);
     else if (ty == 8 && rows == 9)
         hipLaunchKernelGGL((k_step2d<L, P, NS, 8, 9>), dim3(ntiles), dim3(32 * 8), 0, st, insts, tiles, ent);
     else
@@ -1240,11 +1242,11 @@ int tile_options(int lattice, bool compacted, int* ty, int* cz, int cap)
     // 2D: (lanes / 32, 0) for fixed 64 x TY tiles, (lanes / 32, rows) for packed tiles of at
     // most `rows` rows; 3D: (TY, planes per workgroup), TY = 12 and 16 for the fluid-compacted
     // columns (global-shift storage in 32 or 16 bits only)
-    static const int t2[5][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 9}, {8, 12}};
+    static const int t2[6][2] = {{4, 0}, {8, 0}, {16, 0}, {8, 9}, {8, 12}, {16, 24}};
     static const int t3[11][2] = {{4, 16}, {4, 32}, {8, 16}, {8, 32}, {8, 64}, {8, 128},
                                   {12, 32}, {12, 64}, {16, 16}, {16, 32}, {16, 64}};
     const bool d2 = lattice == 0 || lattice == 2;  // D2Q9 and D2Q5 share the 2D launch shapes
-    const int total = d2 ? 5 : (compacted ? 11 : 6);
+    const int total = d2 ? 6 : (compacted ? 11 : 6);
     for (int i = 0; i < total && i < cap; ++i) {
         if (ty) ty[i] = d2 ? t2[i][0] : t3[i][0];
         if (cz) cz[i] = d2 ? t2[i][1] : t3[i][1];
