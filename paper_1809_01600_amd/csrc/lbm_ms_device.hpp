@@ -198,8 +198,8 @@ __device__ inline void gstore(void* base, unsigned byte_off, T v)
 // per-launch arguments
 // ---------------------------------------------------------------------------------------------
 struct StepArgs {
-    const void* fin;          // post-collision populations of step t   [2][Q][P] (fluid nodes)
-    void* fout;               // post-collision populations of step t+1 [2][Q][P]
+    const void* fin;          // post-collision populations of step t   [Q][P][2] (fluid nodes)
+    void* fout;               // post-collision populations of step t+1 [Q][P][2]
     const double* xin;        // node reference c of step t   [2][NF] (NODE shift only)
     double* xout;             // node reference c of step t+1 [2][NF]
     const int* idx;           // dense [N]: compact fluid index of the node, -1 for solid

@@ -5,11 +5,11 @@
 // moments, takes the mole-fraction gradients from an LDS tile that also holds a one-node halo
 // (recomputed from the halo nodes' own pulls), solves the Maxwell-Stefan system in FP64 for the
 // relaxation times, collides and stores to the other buffer.  Populations of fluid nodes only
-// are stored, structure of arrays [species][link][fluid node] with the fluid nodes numbered in
-// raster order (x fastest) in 2D and, in 3D, column by column of 64 x 16 voxels, plane by plane
-// and in raster order within a plane; a dense int32 map gives each voxel's fluid index (-1 =
-// solid), so solid voxels cost no population traffic while a wavefront's loads and stores stay
-// contiguous along x.
+// are stored, one array per link with the two species of a node side by side ([link][fluid
+// node][species]); fluid nodes are numbered in raster order (x fastest) in 2D and, in 3D, column
+// by column of 64 x 16 voxels, plane by plane and in raster order within a plane.  A dense int32
+// map gives each voxel's fluid index (-1 = solid), so solid voxels cost no population traffic
+// while a wavefront's loads and stores stay contiguous along x.
 #include <hip/hip_runtime.h>
 #include <type_traits>
 
