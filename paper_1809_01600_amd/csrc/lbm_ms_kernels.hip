@@ -724,28 +724,53 @@ __global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* 
         plane_of(r + 1, st_n, cnt_n);
         p_n = l < cnt_n ? cpos[st_n + l] : 0;
         // first pass of plane it+1 (populations kept) and, if it is output, its halo ring; all
-        // loads issued before any is used
+        // loads issued before any is used.  Halo position h goes to lane (cnt + h) mod 512, the
+        // lanes after the plane's own nodes (and after a second pass's, which start at lane 0),
+        // so that waves with few or no own nodes take it; a wave with neither skips its loads.
         const bool own_n = l < cnt;
         const int cxn = pn & 63, cyn = pn >> 6, xn = x0 + cxn;
         const int in_ = own_n ? index_at(r, cxn, cyn) : -1;
         int si[L::Q];
         const uint32_t nbn = lds_sources<L, RX, RY, NPL>(sI, r, cxn + 2, cyn + 2, xn, a.nx, in_, si);
-        const bool hwave = need_next && l < HWAVES * 64;  // uniform per wave
-        const int hi = (hwave && hjob) ? index_at(r, hx, hy) : -1;
+        const int hl = (l - cnt) & (NT - 1);
         CT fn[2][L::Q];
-        double Xp0, Xp1, h0 = 0.0, h1 = 0.0;
+        double Xp0 = 0.0, Xp1 = 0.0, h0 = 0.0, h1 = 0.0;
+        int hoff = -1, hi = -1;  // the halo position's offset in a moment plane, its fluid index
+        bool hin = false, hout = false;
         {
             raw rn[2][L::Q], rh[2][L::Q];
-            gather_issue<L, P>(a, in_ < 0 ? 0 : in_, si, xn == 0, xn == a.nx - 1, rn);
-            if (hwave) {
-                int hsi[L::Q];
-                lds_sources<L, RX, RY, NPL>(sI, r, hx + 2, hy + 2, hgx, a.nx, hi, hsi);
-                gather_issue<L, P>(a, hi < 0 ? 0 : hi, hsi, hjob && hgx == 0, hjob && hgx == a.nx - 1, rh);
-            }
-            gather_finish<L, P>(a, rn, xn == 0, xn == a.nx - 1, fn, Xp0, Xp1);
-            if (hwave) {
-                CT hf[2][L::Q];
-                gather_finish<L, P>(a, rh, hjob && hgx == 0, hjob && hgx == a.nx - 1, hf, h0, h1);
+            auto halo_issue = [&]() {
+                if (need_next && hl < NHALO) {
+                    int qx, qy;
+                    halo_pos<TX, TY>(hl, qx, qy);
+                    if (qy == TY) qy = rows;
+                    hoff = (qy + 1) * (TX + 2) + qx + 1;
+                    const int qgx = x0 + qx;
+                    if (qgx >= 0 && qgx < a.nx && qy <= rows) hi = index_at(r, qx, qy);
+                    hin = hi >= 0 && qgx == 0;
+                    hout = hi >= 0 && qgx == a.nx - 1;
+                    int hsi[L::Q];
+                    lds_sources<L, RX, RY, NPL>(sI, r, qx + 2, qy + 2, qgx, a.nx, hi, hsi);
+                    gather_issue<L, P>(a, hi < 0 ? 0 : hi, hsi, hin, hout, rh);
+                }
+            };
+            auto halo_finish = [&]() {
+                if (hoff >= 0) {
+                    CT hf[2][L::Q];
+                    gather_finish<L, P>(a, rh, hin, hout, hf, h0, h1);
+                }
+            };
+            // a wave without a node of plane it+1 (a scalar test on its first lane) skips the pull
+            if ((__builtin_amdgcn_readfirstlane(l) & ~63) < cnt) {
+                gather_issue<L, P>(a, in_ < 0 ? 0 : in_, si, xn == 0, xn == a.nx - 1, rn);
+                halo_issue();
+                gather_finish<L, P>(a, rn, xn == 0, xn == a.nx - 1, fn, Xp0, Xp1);
+                halo_finish();
+            } else {
+                halo_issue();
+#pragma unroll
+                for (int k = 0; k < L::Q; ++k) fn[0][k] = fn[1][k] = CT(0);
+                halo_finish();
             }
         }
         if (in_ < 0) Xp0 = Xp1 = 0.0;
@@ -755,9 +780,9 @@ __global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* 
             sX[sn][0][cyn + 1][cxn + 1] = Xp0;
             sX[sn][1][cyn + 1][cxn + 1] = Xp1;
         }
-        if (hwave && l < NHALO) {
-            sX[sn][0][hy + 1][hx + 1] = h0;
-            sX[sn][1][hy + 1][hx + 1] = h1;
+        if (hoff >= 0) {
+            (&sX[sn][0][0][0])[hoff] = h0;
+            (&sX[sn][1][0][0])[hoff] = h1;
         }
         // second pass of plane it+1: moments only
         for (int k = l + NT; k < cnt; k += NT) moments_to_ring(r, cpos[st + k]);
