@@ -6,8 +6,9 @@
 // (recomputed from the halo nodes' own pulls), solves the Maxwell-Stefan system in FP64 for the
 // relaxation times, collides and stores to the other buffer.  Populations of fluid nodes only
 // are stored, one array per link with the two species of a node side by side ([link][fluid
-// node][species]); fluid nodes are numbered in raster order (x fastest) in 2D and, in 3D, column
-// by column of 64 x 16 voxels, plane by plane and in raster order within a plane.  A dense int32
+// node][species]); fluid nodes are numbered strip by strip of 64 voxels in x in 2D (raster order
+// within a strip) and, in 3D, column by column of 64 x 16 voxels, plane by plane, each plane's
+// two x-edge lines first and then its rows in raster order.  A dense int32
 // map gives each voxel's fluid index (-1 = solid), so solid voxels cost no population traffic
 // while a wavefront's loads and stores stay contiguous along x.
 #include <hip/hip_runtime.h>

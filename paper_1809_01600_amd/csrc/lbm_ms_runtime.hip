@@ -23,7 +23,7 @@ namespace {
 constexpr double R_GAS = 8.3145;    // J / (mol K)
 constexpr double FARADAY = 96485.0; // C / mol (Eq. 39)
 constexpr int RED_BLOCKS = 1024;    // per-block partials of the reductions
-constexpr uint64_t STATE_MAGIC = 0x334d534c42304c31ull;
+constexpr uint64_t STATE_MAGIC = 0x334d534c42304c32ull;
 
 struct Layout {
     size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
@@ -462,20 +462,26 @@ long long clean_pores(const lbm_ms_params& p, std::vector<uint8_t>& solid)
 }
 
 // Fluid nodes of a 2D box are numbered in raster order (x fastest).  A 3D box is numbered by
-// columns of 64 x 16 voxels (x-column fastest, then y), each column plane by plane: the nodes a
-// marching workgroup pulls in one plane then sit together in memory instead of sharing cache
-// lines with the columns beside it, which march out of step.  Within a column's plane come first
-// its two edge lines x = x0 and x = x0 + 63 (y increasing; the voxels a neighbouring column
-// reads as its side halo, now one short run each), then the rows between in raster order.
-// Solid voxels map to -1.
+// Fluid-node numbering.  2D: strips 64 voxels wide (the width of a work-list tile), strip by
+// strip, each in raster order, so that a tile's nodes are one contiguous run of each link's
+// array and no cache line is shared with the tile beside it in x (with raster order over the
+// whole box each tile row was a short run whose end lines the neighbouring tile, processed at
+// another time, read and wrote again).  3D: columns of 64 x 16 voxels (x-column fastest, then
+// y), each column plane by plane: the nodes a marching workgroup pulls in one plane then sit
+// together in memory instead of sharing cache lines with the columns beside it, which march out
+// of step.  Within a column's plane come first its two edge lines x = x0 and x = x0 + 63 (y
+// increasing; the voxels a neighbouring column reads as its side halo, now one short run each),
+// then the rows between in raster order.  Solid voxels map to -1.
 long long build_index(const std::vector<uint8_t>& solid, int nx, int ny, int nz,
                       std::vector<int32_t>& idx)
 {
     idx.assign(solid.size(), -1);
     long long k = 0;
     if (nz == 1) {
-        for (size_t n = 0; n < solid.size(); ++n)
-            if (!solid[n]) idx[n] = (int32_t)k++;
+        for (int x0 = 0; x0 < nx; x0 += COL_X)
+            for (int y = 0; y < ny; ++y)
+                for (int x = x0; x < std::min(x0 + COL_X, nx); ++x)
+                    if (!solid[(size_t)y * nx + x]) idx[(size_t)y * nx + x] = (int32_t)k++;
         return k;
     }
     for (int y0 = 0; y0 < ny; y0 += COL_Y)
