@@ -45,7 +45,8 @@ WORKLOAD_LATTICES = {"porous_2d": ("D2Q9", "D2Q5"), "porous_3d": ("D3Q19", "D3Q7
                      "batch_2d": ("D2Q9",), "steady": ("D2Q9",)}
 NODE_SHIFT_BYTES = 2 * 8 * 2
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
-                  "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip"]
+                  "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip",
+                  "paper_1809_01600_amd/csrc/lbm_ms_runtime.hip"]  # the node numbering
 
 
 def kernel_hash() -> str:

@@ -544,9 +544,10 @@ void build_tiles_2d(int nx, int ny, int ty, int rows, const std::vector<uint8_t>
             if (x < nx && fluid(x, y)) own.push_back((uint32_t)(cy << 8 | cx));
         }
     };
-    // Tiles are listed in row-band order (y0, then x0): fluid nodes are numbered in raster order,
-    // so horizontally adjacent tiles share the cache lines of each row and should run close together
-    // in time and on one XCD (strip-major order fetched 1.9x the algorithmic bytes instead of 1.2x).
+    // Tiles are listed in row-band order (y0, then x0), so the tiles that run together on one XCD
+    // span the box in x.  With fluid nodes numbered in 64-wide strips (build_index) a tile's
+    // nodes are one run per link and its halo rows sit in the runs of the tiles above and below
+    // it; listing the tiles strip by strip instead measured 1% slower.
     if (rows > 0) {
         const size_t first = tiles.size();
         for (int x0 = 0; x0 < nx; x0 += TX)
