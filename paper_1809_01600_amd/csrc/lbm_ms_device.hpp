@@ -193,6 +193,12 @@ __device__ inline void gstore(void* base, unsigned byte_off, T v)
 {
     *(LBMMS_GLOBAL T*)((LBMMS_GLOBAL char*)base + byte_off) = v;
 }
+// a store marked non-temporal: the line is not kept in the L2 for reuse
+template <class T>
+__device__ inline void gstore_nt(void* base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, (LBMMS_GLOBAL T*)((LBMMS_GLOBAL char*)base + byte_off));
+}
 
 // ---------------------------------------------------------------------------------------------
 // per-launch arguments
@@ -652,8 +658,10 @@ __device__ inline double grad1(bool up, bool dn, double xu, double xc, double xd
 // a shift of the equilibrium: f + omega (w X - f) + w S = f + omega (w (X + S / omega) - f).
 // NODE shift: f holds g_a = f_a - w_a X, so f*_a = w_a (X + S) + (1 - omega) g_a; the deviations
 // are rounded to the storage precision and the node reference c = X + S - sum_a h_a (FP64)
-// keeps the stored moment equal to X + S whatever the rounding.
-template <class L, int P, bool NS>
+// keeps the stored moment equal to X + S whatever the rounding.  NT: global-shift stores marked
+// non-temporal (the compacted 3D columns, whose next plane re-reads lines the L2 would otherwise
+// give up to the stores).
+template <class L, int P, bool NS, bool NT = false>
 __device__ inline void collide_store(const StepArgs& a, int n,
                                      typename Codec<P>::CT (&f)[2][L::Q], double X0, double X1,
                                      double om0, double om1, double s0, double s1)
@@ -728,6 +736,9 @@ __device__ inline void collide_store(const StepArgs& a, int n,
                     const float wf = L::wf[k];
                     gstore<raw>(fout, off, C::enc(v0, wf * c0));
                     gstore<raw>(fout, off + spec, C::enc(v1, wf * c1));
+                } else if constexpr (NT) {
+                    gstore_nt<raw>(fout, off, C::enc(v0, CT(0)));
+                    gstore_nt<raw>(fout, off + spec, C::enc(v1, CT(0)));
                 } else {
                     gstore<raw>(fout, off, C::enc(v0, CT(0)));
                     gstore<raw>(fout, off + spec, C::enc(v1, CT(0)));

@@ -795,7 +795,7 @@ __global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* 
             double om0, om1;
             relax(it, cx, cy, nbc, Xc0, Xc1, x == a.nx - 1, om0, om1);
             const bool src = x >= a.src_x0;
-            collide_store<L, P, false>(a, ic, fc, Xc0, Xc1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
+            collide_store<L, P, false, P == P_F32>(a, ic, fc, Xc0, Xc1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
         }
         // ... and the second pass, pulled again
         for (int k = l + NT; k < cnt_c; k += NT) {
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(512, 1) void k_step3dc(StepArgs a, const unsigned* 
             gather<L, P, false>(a, i, ssi, x == 0, x == a.nx - 1, f, X0, X1);
             relax(it, cx, cy, nb, X0, X1, x == a.nx - 1, om0, om1);
             const bool src = x >= a.src_x0;
-            collide_store<L, P, false>(a, i, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
+            collide_store<L, P, false, P == P_F32>(a, i, f, X0, X1, om0, om1, src ? a.S0 : 0.0, src ? a.S1 : 0.0);
         }
         ic = in_;
         pc = pn;
