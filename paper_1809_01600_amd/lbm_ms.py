@@ -237,8 +237,11 @@ def work_list(lattice: str, solid: np.ndarray, tile_y: int, rows: int):
     return tiles, ent[:ne.value]
 
 
-def tile_options(lattice: int, precision=FP32, shift_mode: int = SHIFT_GLOBAL):
-    """Compiled launch shapes (tile_y, chunk_z) for a lattice and storage mode."""
+def tile_options(lattice, precision=FP32, shift_mode: int = SHIFT_GLOBAL):
+    """Compiled launch shapes (tile_y, chunk_z) for a lattice and storage mode (lattice and
+    precision as constants or names)."""
+    if isinstance(lattice, str):
+        lattice = LATTICES[lattice]
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     ty = (ctypes.c_int * 16)()
