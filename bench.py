@@ -422,21 +422,29 @@ def run_steady(args):
     import torch
     from paper_1809_01600_amd import cnn, lbm_ms, warmstart
     quiet = lambda m: None  # noqa: E731
+
+    def phase(m):  # progress on stderr; the JSON line stays alone on stdout
+        print("steady: %s (%.1f s)" % (m, time.perf_counter() - t0), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    phase("generating 256 steady 64^2 training slices")
     feat, tgt, fluid = warmstart.generate(256, 64, 50000, chunk=128, tol=1e-9, log=quiet)
+    phase("training the network")
     net = cnn.WarmStartNet(seed=0)
     warmstart.train(net, feat, tgt, fluid, epochs=12, batch=16, lr=2e-3, log=quiet)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del feat, tgt, fluid
     cases = warmstart.make_cases(args.steady_n, args.steady_side, 60000)
+    phase("FP64 references to r = 1e-11")
     ref, _, _ = warmstart.solve(cases, tol=1e-11, precision="fp64", max_steps=8_000_000)
     keep = [k for k in range(len(cases)) if ref.status[k] == 0]
     eta_ref = ref.overpotential()[keep]
     ref.close()
     cases = [cases[k] for k in keep]
     tol = args.steady_tol
+    phase("plain form")
     st_p, stat_p, eta_p, sec_p = warmstart.solve_plain(cases, tol=tol, precision="fp32")
+    phase("batched, warm-started form")
     fast, st_f, sec_f = warmstart.solve(cases, X0=warmstart.cnn_start(net, cases), tol=tol,
                                         precision="fp16", shift_mode=lbm_ms.SHIFT_NODE)
     eta_f = fast.overpotential()
