@@ -44,6 +44,20 @@ BYTES_PER_NODE = {("D2Q9", "fp64"): 288, ("D2Q9", "fp32"): 144, ("D2Q9", "fp16")
 WORKLOAD_LATTICES = {"porous_2d": ("D2Q9", "D2Q5"), "porous_3d": ("D3Q19", "D3Q7"),
                      "batch_2d": ("D2Q9",), "steady": ("D2Q9",)}
 NODE_SHIFT_BYTES = 2 * 8 * 2
+# --advection: a reaction that changes the number of moles (nu = -1, 2, 0), so a net molar flux
+# drives u_M, carried by the second lattice Boltzmann model (relaxation time ADV_TAU_FLOW)
+ADV_NU = (-1, 2, 0)
+ADV_TAU_FLOW = 1.0
+
+
+def adv_bytes_per_node(lattice: str, precision: str) -> int:
+    """Algorithmic bytes of one advective step per fluid node: both species' populations and the
+    velocity model's read and written once (6 Q entries), and the node velocity of the previous
+    step read and of this step written (2 x 3 doubles).  The two-pass kernels also write and read
+    back X (2 doubles) and pull the species twice; that traffic is theirs, not the method's."""
+    q = {"D2Q9": 9, "D2Q5": 5, "D3Q19": 19, "D3Q7": 7}[lattice]
+    es = 8 if precision == "fp64" else 4
+    return 6 * q * es + 48
 KERNEL_SOURCES = ["paper_1809_01600_amd/csrc/lbm_ms_device.hpp",
                   "paper_1809_01600_amd/csrc/lbm_ms_kernels.hip",
                   "paper_1809_01600_amd/csrc/lbm_ms_runtime.hip"]  # the node numbering
@@ -93,7 +107,7 @@ def _host_cores() -> int:
     return max(1, min(n, 16))
 
 
-def _oracle_sample(case, steps: int):
+def _oracle_sample(case, steps: int, advection: bool = False):
     """Oracle steps on one problem (or the first 32 z-planes of a 3D block as a periodic slab);
     returns (fluid nodes, steps, seconds)."""
     import dataclasses
@@ -102,7 +116,7 @@ def _oracle_sample(case, steps: int):
     sample = case
     if case.nz > 32:
         sample = dataclasses.replace(case, nz=32, solid=np.ascontiguousarray(case.mask()[:32]))
-    o = oracle.Oracle(sample)
+    o = oracle.Oracle(sample, advection=advection, tau_flow=ADV_TAU_FLOW)
     o.init_uniform()
     o.step(1)  # warm-up (allocations, page faults)
     t0 = time.perf_counter()
@@ -126,12 +140,12 @@ def _oracle_timed(case, seconds: float):
             return int(o.fluid().sum()), steps, dt
 
 
-def cpu_baseline(case, steps: int):
+def cpu_baseline(case, steps: int, advection: bool = False):
     """The FP64 CPU oracle as it stands, single thread, on a bounded sample of the workload:
     `steps` steps of the whole slice (2D), or of the block's first 32 z-planes stepped as a
     periodic slab (3D: the whole 256^3 block takes the oracle about a minute per step and 15 GB
     of memory)."""
-    n_fluid, steps, dt = _oracle_sample(case, steps)
+    n_fluid, steps, dt = _oracle_sample(case, steps, advection)
     if case.nz == 1:
         what = "the same %dx%d slice" % (case.nx, case.ny)
     else:
@@ -139,7 +153,8 @@ def cpu_baseline(case, steps: int):
             case.nx, case.ny, case.nz)
     return {"value": 2.0 * n_fluid * steps / dt / 1e6, "unit": "species-MLUPS", "cores": 1,
             "kind": "oracle", "cpu_model": _cpu_model(),
-            "sample": "%d steps of %s (%d fluid nodes), FP64, single thread" % (steps, what, n_fluid)}
+            "sample": "%d %ssteps of %s (%d fluid nodes), FP64, single thread" % (
+                steps, "advective " if advection else "", what, n_fluid)}
 
 
 def cpu_baseline_batch(cases, seconds: float = 12.0):
@@ -197,7 +212,14 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="seconds each oracle worker steps in the batch CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--advection", action="store_true",
+                    help="porous_2d / porous_3d with a net molar flux (nu = -1, 2, 0) and the "
+                         "advective coupling of Eq. 26 (FP64 or FP32 storage)")
     args = ap.parse_args(argv)
+    if args.advection and args.workload not in ("porous_2d", "porous_3d"):
+        ap.error("--advection takes --workload porous_2d or porous_3d")
+    if args.advection and (args.precision not in ("fp64", "fp32") or args.shift != "global"):
+        ap.error("--advection runs with FP64 or FP32 global storage")
     lattices = WORKLOAD_LATTICES[args.workload]
     if args.lattice and args.lattice.upper() not in lattices:
         ap.error("--workload %s takes --lattice %s" % (args.workload, " or ".join(l.lower() for l in lattices)))
@@ -238,8 +260,14 @@ def main(argv=None):
         desc = ("porous anode block %s 256^3, overlapping spheres r~U[3,8], void fraction "
                 "~U[0.35,0.50], seed 3, X_in=(0.6,0.3,0.1), j=1.0 A/cm^2" % case.lattice)
     shift = lbm_ms.SHIFT_NODE if args.shift == "node" else lbm_ms.SHIFT_GLOBAL
-    s = lbm_ms.Solver(case, precision=args.precision, shift_mode=shift, tile_y=args.tile_y,
-                      chunk_z=args.chunk_z)
+    if args.advection:
+        import dataclasses
+        case = dataclasses.replace(case, nu=ADV_NU)
+        desc += ", nu=(-1,2,0) with the advective coupling (Eq. 26, velocity model tau %.1f)" % ADV_TAU_FLOW
+        s = lbm_ms.Solver(case, precision=args.precision, advection=True, tau_flow=ADV_TAU_FLOW)
+    else:
+        s = lbm_ms.Solver(case, precision=args.precision, shift_mode=shift, tile_y=args.tile_y,
+                          chunk_z=args.chunk_z)
     info = s.get_info()
     n_fluid = int(info.n_fluid)
     s.init()
@@ -273,9 +301,12 @@ def main(argv=None):
     bytes_per_launch = BYTES_PER_NODE[(case.lattice, args.precision)] * n_fluid
     if shift == lbm_ms.SHIFT_NODE:  # FP64 node reference per evolved species, read and written
         bytes_per_launch += NODE_SHIFT_BYTES * n_fluid
+    if args.advection:  # the step's two kernels together, timed as one
+        bytes_per_launch = adv_bytes_per_node(case.lattice, args.precision) * n_fluid
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     alt = "" if case.lattice == lattices[0] else "_" + case.lattice.lower()
-    wl_key = "%s%s_%s_%s" % (args.workload, alt, args.precision, args.shift)
+    wl_key = "%s%s_%s_%s%s" % (args.workload, alt, args.precision, args.shift,
+                               "_advection" if args.advection else "")
     traffic = measured_traffic(wl_key, kernel_hash())
 
     ms_per_step = elapsed * 1e3 / K
@@ -316,14 +347,16 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": ("k_step3dc" if int(info.tile_y) in (12, 16) else "k_step3d") if case.nz > 1
-                      else "k_step2d",
+            "kernel": "k_adv_moments+k_adv_step" if args.advection else
+                      (("k_step3dc" if int(info.tile_y) in (12, 16) else "k_step3d") if case.nz > 1
+                       else "k_step2d"),
             "kernel_us": round(kernel_ms * 1e3, 3),
             "bytes_per_launch": bytes_per_launch,
         },
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps or (40 if case.nz == 1 else 6))
+        default_steps = (20 if case.nz == 1 else 3) if args.advection else (40 if case.nz == 1 else 6)
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps or default_steps, args.advection)
     print(json.dumps(line), flush=True)
     s.close()
     return 0

@@ -126,15 +126,15 @@ __device__ inline void ms_relax_adv(const StepArgs& a, const AdvArgs& v, double 
 
 }  // namespace
 
-// pass 1: X of every fluid node (species pull with its boundary rules)
+// pass 1: X of every fluid node (species pull with its boundary rules).  Both passes run one
+// thread per fluid node (vox gives its voxel), so no lane idles on a solid voxel.
 template <class L, int P>
-__global__ __launch_bounds__(256) void k_adv_moments(StepArgs a, double* xw)
+__global__ __launch_bounds__(256) void k_adv_moments(StepArgs a, const int* __restrict__ vox, double* xw)
 {
     using CT = typename Codec<P>::CT;
-    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < a.N;
-         n += (long long)gridDim.x * blockDim.x) {
-        const int i = a.idx[n];
-        if (i < 0) continue;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.NF;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long n = vox[i];
         int x, y, z;
         voxel_xyz(a, n, x, y, z);
         CT f[2][L::Q];
@@ -156,10 +156,10 @@ __global__ __launch_bounds__(256) void k_adv_step(StepArgs a, AdvArgs v)
     const unsigned plane = (unsigned)a.P * ES;             // velocity model: [Q][P]
     const unsigned link = pop_link<ES>(a);                   // species: the population layout
     const unsigned spec = pop_spec<L, ES>(a);
-    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < a.N;
-         n += (long long)gridDim.x * blockDim.x) {
-        const int i = a.idx[n];
-        if (i < 0) continue;
+    for (long long ii = blockIdx.x * (long long)blockDim.x + threadIdx.x; ii < a.NF;
+         ii += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)ii;
+        const long long n = v.vox[i];
         int x, y, z;
         voxel_xyz(a, n, x, y, z);
         int si[L::Q];
@@ -267,10 +267,10 @@ __global__ __launch_bounds__(256) void k_adv_velocity(StepArgs a, const double* 
 template <class L, int P>
 static hipError_t adv_step_l(hipStream_t st, const StepArgs& a, const AdvArgs& v, double* xw)
 {
-    hipLaunchKernelGGL((k_adv_moments<L, P>), dim3(adv_grid(a.N)), dim3(256), 0, st, a, xw);
+    hipLaunchKernelGGL((k_adv_moments<L, P>), dim3(adv_grid(a.NF)), dim3(256), 0, st, a, v.vox, xw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adv_step<L, P>), dim3(adv_grid(a.N)), dim3(256), 0, st, a, v);
+    hipLaunchKernelGGL((k_adv_step<L, P>), dim3(adv_grid(a.NF)), dim3(256), 0, st, a, v);
     return hipGetLastError();
 }
 

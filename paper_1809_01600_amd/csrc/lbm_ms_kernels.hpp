@@ -43,6 +43,7 @@ struct AdvArgs {
     double om_flow;     // 1 / tau_flow
     double nh0, nh1, nh2, nht;  // -nu_s and their sum: the direction of the electrode fluxes
     double eps2;        // square of the flux regularizer
+    const int* vox;     // voxel index of each compact node [NF] (the passes run over fluid nodes)
 };
 // one coupled step: X pass into xw (= v.xc), then the step; FP64 or FP32 storage, every lattice
 hipError_t launch_adv_step(hipStream_t st, const StepArgs& a, const AdvArgs& v, double* xw,

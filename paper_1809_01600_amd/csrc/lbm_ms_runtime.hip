@@ -28,7 +28,8 @@ constexpr uint64_t STATE_MAGIC = 0x334d534c42304c32ull;
 struct Layout {
     size_t f[2], xn[2], idx, snap, field, part, prof, flags, scal, inst, tiles, ent, total;
     size_t tile_cap, ent_cap;
-    size_t g[2], u[2], xa;  // advective coupling: velocity model, node velocities, X per node
+    size_t g[2], u[2], xa, vox;  // advective coupling: velocity model, node velocities, X and
+                                 // voxel per compact node
     size_t c3off, c3pos;    // 3D fluid-compacted columns: plane offsets, in-column positions
 };
 
@@ -213,6 +214,7 @@ Layout layout(const lbm_ms_params& p)
         L.u[0] = take(3ull * N * sizeof(double));
         L.u[1] = take(3ull * N * sizeof(double));
         L.xa = take(2ull * N * sizeof(double));
+        L.vox = take(N * sizeof(int32_t));
     }
     L.total = off;
     return L;
@@ -328,6 +330,7 @@ struct lbm_ms_s {
         v.nh2 = -(double)p.nu[2];
         v.nht = v.nh0 + v.nh1 + v.nh2;
         v.eps2 = eps * eps;
+        v.vox = p.advection ? reinterpret_cast<const int*>(ws + L.vox) : nullptr;
         return v;
     }
     int nblocks_step() const
@@ -882,6 +885,17 @@ int lbm_ms_set_geometry(lbm_ms_t h, const uint8_t* solid_host)
     int rc = h->hip(hipMemcpyAsync(h->at(h->L.idx), idx.data(), idx.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, h->stream), "index upload");
     if (rc) return rc;
+    std::vector<int32_t> vox;
+    if (h->p.advection) {  // the voxel of each compact node, for the advective passes
+        vox.assign((size_t)h->n_fluid, 0);
+        for (size_t n = 0; n < idx.size(); ++n)
+            if (idx[n] >= 0) vox[(size_t)idx[n]] = (int32_t)n;
+        if (!vox.empty()) {
+            rc = h->hip(hipMemcpyAsync(h->at(h->L.vox), vox.data(), vox.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, h->stream), "voxel list upload");
+            if (rc) return rc;
+        }
+    }
     rc = h->sync();
     if (rc) return rc;
     h->geom = true;
