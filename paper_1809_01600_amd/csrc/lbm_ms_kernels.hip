@@ -114,6 +114,53 @@ __device__ inline void stage_store(const PlaneRegs<RX, RY, NT>& r, int* dst)
     }
 }
 
+// stage_plane of a 2D box in chunks of four ints: thread t stages chunk t (row t / (RX / 4), ints
+// 4 (t % (RX / 4)) .. + 3 of it), with one 16-byte load where the chunk lies inside the box in x
+// (the map's rows are only 4-byte aligned; gfx950 loads such a vector in one instruction) and
+// element by element at the box's x faces; a quarter of the load instructions of stage_issue.
+typedef int int4u __attribute__((ext_vector_type(4), aligned(4)));
+template <int RX, int RY, int NT>
+struct PlaneRegs4 {
+    static constexpr int NC = RY * (RX / 4);  // chunks in the region
+    int4u v[(NC + NT - 1) / NT];
+};
+template <int RX, int RY, int NT>
+__device__ inline void stage_issue4(const StepArgs& a, int x0, int y0, PlaneRegs4<RX, RY, NT>& r)
+{
+    static_assert(RX % 4 == 0, "rows of whole chunks");
+    constexpr int CR = RX / 4, NC = PlaneRegs4<RX, RY, NT>::NC;
+    const int nx = a.nx, ny = a.ny;
+    const int* idx = a.idx;
+#pragma unroll
+    for (int j = 0; j < (NC + NT - 1) / NT; ++j) {
+        const int c = threadIdx.x + j * NT;
+        const int ry = c / CR, gx = x0 - 2 + 4 * (c % CR);
+        const int gy = wrap_row<RY>(y0 - 2 + ry, ny);
+        const unsigned base = (unsigned)(gy * nx + gx) * 4u;  // a 2D box: one plane
+        int4u v = {-2, -2, -2, -2};
+        if (c < NC) {
+            if (gx >= 0 && gx + 3 < nx) {
+                v = *(const LBMMS_GLOBAL int4u*)((const LBMMS_GLOBAL char*)idx + base);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (gx + e >= 0 && gx + e < nx) v[e] = gload<int>(idx, base + 4u * (unsigned)e);
+            }
+        }
+        r.v[j] = v;
+    }
+}
+template <int RX, int RY, int NT>
+__device__ inline void stage_store4(const PlaneRegs4<RX, RY, NT>& r, int* dst)
+{
+    constexpr int CR = RX / 4, NC = PlaneRegs4<RX, RY, NT>::NC;
+#pragma unroll
+    for (int j = 0; j < (NC + NT - 1) / NT; ++j) {
+        const int c = threadIdx.x + j * NT;
+        if (c < NC) *(int4*)(dst + (c / CR) * RX + 4 * (c % CR)) = make_int4(r.v[j].x, r.v[j].y, r.v[j].z, r.v[j].w);
+    }
+}
+
 // The index maps of planes z0 - 2 .. z0 + 2 into ring slots (zr + 2) % NPL, every load issued
 // before the first store (a loop of load, wait and store per element would take one memory round
 // trip per element a thread stages).
@@ -298,7 +345,7 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
 {
     using CT = typename Codec<P>::CT;
     constexpr int TX = 64, RX = TX + 4, RY = TYR + 4, BS = 32 * TY;
-    __shared__ int sI[RY * RX];
+    __shared__ __align__(16) int sI[RY * RX];
     __shared__ double sX[2][TYR + 2][TX + 2];
     __shared__ double sC[NS ? 2 * RY * RX : 1];  // NODE shift: staged references
 
@@ -320,9 +367,9 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
     if constexpr (NS) {
         stage_plane_refs_pipelined<RX, RY, BS>(a, x0, y0, sI, sC);
     } else {
-        PlaneRegs<RX, RY, BS> stg;
-        stage_issue<RX, RY, BS>(a, x0, y0, 0, stg);
-        stage_store<RX, RY, BS>(stg, sI);
+        PlaneRegs4<RX, RY, BS> stg;
+        stage_issue4<RX, RY, BS>(a, x0, y0, stg);
+        stage_store4<RX, RY, BS>(stg, sI);
     }
     __syncthreads();
 
