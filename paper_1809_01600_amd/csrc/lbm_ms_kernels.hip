@@ -981,13 +981,11 @@ __device__ inline void block_reduce_store(double (&v)[NV], double* out)
 //   0: sum (X - Xsnap)^2, 1: sum X^2, 2: inventory 1, 3: inventory 2, 4: non-finite count,
 //   5: negative-fraction count
 template <class L, int P, bool NS>
-__global__ __launch_bounds__(256) void k_residual(StepArgs a, double* snap, int update,
-                                                  double* partial)
+__device__ inline void residual_sums(const StepArgs& a, double* snap, int update, long long first,
+                                     long long stride, double (&v)[6])
 {
-    double v[6] = {0, 0, 0, 0, 0, 0};
     const long long NF = a.NF;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < NF;
-         i += (long long)gridDim.x * blockDim.x) {
+    for (long long i = first; i < NF; i += stride) {
         double X0, X1;
         node_moments<L, P, NS>(a, (int)i, X0, X1);
         const double X2 = 1.0 - X0 - X1;
@@ -1004,7 +1002,30 @@ __global__ __launch_bounds__(256) void k_residual(StepArgs a, double* snap, int 
         v[4] += finite ? 0.0 : 1.0;
         v[5] += (X0 < -1e-12 || X1 < -1e-12 || X2 < -1e-12) ? 1.0 : 0.0;
     }
+}
+template <class L, int P, bool NS>
+__global__ __launch_bounds__(256) void k_residual(StepArgs a, double* snap, int update,
+                                                  double* partial)
+{
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    residual_sums<L, P, NS>(a, snap, update, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+                            (long long)gridDim.x * blockDim.x, v);
     block_reduce_store<6>(v, partial + (long long)blockIdx.x * 8);
+}
+// k_residual for every instance of a batch at once: nblocks workgroups per instance, each doing
+// what workgroup b of the instance's own k_residual does (the same sums in the same order)
+template <class L, int P, bool NS>
+__global__ __launch_bounds__(256) void k_residual_batch(const StepArgs* __restrict__ tab,
+                                                        const ResidualSlot* __restrict__ slots,
+                                                        int nblocks, int update)
+{
+    const int k = blockIdx.x / nblocks, b = blockIdx.x - k * nblocks;
+    const ResidualSlot& s = slots[k];
+    if (!s.active) return;  // the whole workgroup
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    residual_sums<L, P, NS>(tab[k], s.snap, update, b * (long long)blockDim.x + threadIdx.x,
+                            (long long)nblocks * blockDim.x, v);
+    block_reduce_store<6>(v, s.partial + (long long)b * 8);
 }
 
 // fixed-order sum of the per-block partials (one workgroup)
@@ -1016,6 +1037,21 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int nbl
         for (int i = 0; i < 8; ++i)
             if (i < nv) v[i] += partial[(long long)b * 8 + i];
     block_reduce_store<8>(v, out);
+}
+
+// k_finalize of each instance of a batch (workgroup k), plus its first 16 flag bytes
+__global__ __launch_bounds__(256) void k_finalize_batch(const ResidualSlot* __restrict__ slots,
+                                                        int nblocks, double* out)
+{
+    const ResidualSlot& s = slots[blockIdx.x];
+    if (!s.active) return;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int i = 0; i < 8; ++i)
+            if (i < 6) v[i] += s.partial[(long long)b * 8 + i];
+    double* o = out + (long long)blockIdx.x * 16;
+    block_reduce_store<8>(v, o);
+    if (threadIdx.x < 4) reinterpret_cast<unsigned*>(o + 8)[threadIdx.x] = s.flags[threadIdx.x];
 }
 
 // outlet-column means and boundary balances, over the y-z face (one thread per face node)
@@ -1206,6 +1242,13 @@ struct Ops {
                                double* partial, int nblocks)
     {
         hipLaunchKernelGGL((k_residual<L, P, NS>), dim3(nblocks), dim3(256), 0, st, a, snap, update, partial);
+        return hipGetLastError();
+    }
+    static hipError_t residual_batch(hipStream_t st, const StepArgs* tab, const ResidualSlot* slots,
+                                     int count, int update, int nblocks)
+    {
+        hipLaunchKernelGGL((k_residual_batch<L, P, NS>), dim3(count * nblocks), dim3(256), 0, st, tab,
+                           slots, nblocks, update);
         return hipGetLastError();
     }
     static hipError_t faces(hipStream_t st, const StepArgs& a, double* partial, int nblocks)
@@ -1403,6 +1446,11 @@ template <class L, int P, bool NS> struct RunResidual {
     static hipError_t run(hipStream_t st, const StepArgs& a, double* snap, int upd, double* part, int nb)
     { return Ops<L, P, NS>::residual(st, a, snap, upd, part, nb); }
 };
+template <class L, int P, bool NS> struct RunResidualBatch {
+    static hipError_t run(hipStream_t st, const StepArgs* tab, const ResidualSlot* slots, int count,
+                          int upd, int nb)
+    { return Ops<L, P, NS>::residual_batch(st, tab, slots, count, upd, nb); }
+};
 template <class L, int P, bool NS> struct RunFaces {
     static hipError_t run(hipStream_t st, const StepArgs& a, double* part, int nb)
     { return Ops<L, P, NS>::faces(st, a, part, nb); }
@@ -1428,6 +1476,16 @@ hipError_t launch_residual(hipStream_t st, const StepArgs& a, int lattice, int p
     hipError_t e = dispatch<RunResidual>(lattice, prec, ns, st, a, snap, update, partial, nblocks);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partial, nblocks, 6, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_batch(hipStream_t st, const StepArgs* tab, const ResidualSlot* slots,
+                                 int count, int lattice, int prec, int ns, int update, int nblocks,
+                                 double* out)
+{
+    hipError_t e = dispatch<RunResidualBatch>(lattice, prec, ns, st, tab, slots, count, update, nblocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize_batch, dim3(count), dim3(256), 0, st, slots, nblocks, out);
     return hipGetLastError();
 }
 

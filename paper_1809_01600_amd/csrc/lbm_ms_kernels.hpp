@@ -24,6 +24,21 @@ hipError_t launch_init(hipStream_t st, const StepArgs& a, int lattice, int prec,
                        const double* X, double u0, double u1);
 hipError_t launch_residual(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
                            double* snap, int update, double* partial, int nblocks, double* out);
+// One instance of a batch in the batched residual check: its window snapshot, its partial sums,
+// its flags and whether it is still on the work list.
+struct ResidualSlot {
+    double* snap;           // X at the window start [2][NF] (updated)
+    double* partial;        // per-block partial sums [nblocks][8]
+    const unsigned* flags;  // the step's flags (the first 16 bytes are copied out)
+    int active;             // 0: the instance left the work list and is skipped
+    int pad;
+};
+// the residual reduction of every active instance in two launches: out[k][0..7] as launch_residual
+// writes them for instance k, out[k][8..9] its first 16 flag bytes; tab = the instance table of
+// the current parity
+hipError_t launch_residual_batch(hipStream_t st, const StepArgs* tab, const ResidualSlot* slots,
+                                 int count, int lattice, int prec, int ns, int update, int nblocks,
+                                 double* out);
 hipError_t launch_faces(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns,
                         double* partial, int nblocks, double* out);
 hipError_t launch_fields(hipStream_t st, const StepArgs& a, int lattice, int prec, int ns, double* X);

@@ -1131,7 +1131,9 @@ int lbm_ms_time_steps(lbm_ms_t h, int64_t nsteps, double* ms)
 }
 
 // runs the residual reduction; vals[0..5] as in k_residual
-static int reduce_state(lbm_ms_t h, int update, double* vals)
+// queues the residual reduction and the read-backs of its sums and of the clamp flag into the
+// pinned buffer (read once the stream has been synchronized)
+static int reduce_launch(lbm_ms_t h, int update)
 {
     StepArgs a = h->args(h->cur);
     int rc = h->hip(launch_residual(h->stream, a, h->p.lattice, h->prec(), h->ns(),
@@ -1141,8 +1143,13 @@ static int reduce_state(lbm_ms_t h, int update, double* vals)
     rc = h->hip(hipMemcpyAsync(h->pinned, h->at(h->L.scal), 8 * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream), "residual readback");
     if (rc) return rc;
-    rc = h->hip(hipMemcpyAsync(h->pinned + 8, h->at(h->L.flags), 16, hipMemcpyDeviceToHost,
-                               h->stream), "flag readback");
+    return h->hip(hipMemcpyAsync(h->pinned + 8, h->at(h->L.flags), 16, hipMemcpyDeviceToHost,
+                                 h->stream), "flag readback");
+}
+
+static int reduce_state(lbm_ms_t h, int update, double* vals)
+{
+    int rc = reduce_launch(h, update);
     if (rc) return rc;
     rc = h->sync();
     if (rc) return rc;
@@ -1150,13 +1157,13 @@ static int reduce_state(lbm_ms_t h, int update, double* vals)
     return LBM_MS_OK;
 }
 
-int lbm_ms_residual(lbm_ms_t h, double* residual)
+// The check of a window whose reduction reduce_launch queued and the stream has completed: the
+// residual from the pinned sums, then the status (the clamp flag is cleared for the next window).
+static int residual_eval(lbm_ms_t h, double* residual)
 {
-    if (!h || !residual) return LBM_MS_E_ARG;
-    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
     double v[6];
-    int rc = reduce_state(h, 1, v);
-    if (rc) return rc;
+    std::memcpy(v, h->pinned, 6 * sizeof(double));
+    int rc = LBM_MS_OK;
     const unsigned clamp = ((const unsigned*)(h->pinned + 8))[0];
     const long long K = h->steps - h->snap_step;
     h->snap_step = h->steps;
@@ -1173,6 +1180,17 @@ int lbm_ms_residual(lbm_ms_t h, double* residual)
         return h->fail(LBM_MS_E_NEG_FRACTION, "%.0f nodes with a mole fraction below -1e-12", v[5]);
     if (clamp) return h->fail(LBM_MS_E_TAU_CLAMP, "a relaxation time hit the clamp");
     return LBM_MS_OK;
+}
+
+int lbm_ms_residual(lbm_ms_t h, double* residual)
+{
+    if (!h || !residual) return LBM_MS_E_ARG;
+    if (!h->ready) return h->fail(LBM_MS_E_STATE, "init first");
+    int rc = reduce_launch(h, 1);
+    if (rc) return rc;
+    rc = h->sync();
+    if (rc) return rc;
+    return residual_eval(h, residual);
 }
 
 int lbm_ms_converge(lbm_ms_t h, double tol, int64_t max_steps, int check_every,
@@ -1429,6 +1447,8 @@ struct lbm_ms_batch_s {
     std::vector<std::vector<int4>> tiles_k;
     char* ws = nullptr;
     size_t off_tab = 0, off_tiles = 0, off_ent = 0;
+    size_t off_slots = 0, off_res = 0;  // batched residual check: slot table, results [count][16]
+    double* pinned = nullptr;           // host copy of the results
     size_t tile_cap = 0, ent_cap = 0;
     int count = 0, ty = 0, rows = 0;  // rows > 0: packed tiles of at most `rows` rows
     std::vector<char> active;
@@ -1513,6 +1533,42 @@ struct lbm_ms_batch_s {
         if (rc) return rc;
         return upload_active_tiles();
     }
+    // the residual slots of the instances (pointers into their workspaces, on / off the list)
+    int upload_slots()
+    {
+        std::vector<ResidualSlot> t(count);
+        for (int k = 0; k < count; ++k) {
+            lbm_ms_s* h = inst[k];
+            t[k].snap = reinterpret_cast<double*>(h->at(h->L.snap));
+            t[k].partial = reinterpret_cast<double*>(h->at(h->L.part));
+            t[k].flags = reinterpret_cast<const unsigned*>(h->at(h->L.flags));
+            t[k].active = active[k] ? 1 : 0;
+            t[k].pad = 0;
+        }
+        int rc = hip(hipStreamSynchronize(stream), "sync");
+        if (rc) return rc;
+        return hip(hipMemcpy(ws + off_slots, t.data(), t.size() * sizeof(ResidualSlot),
+                             hipMemcpyHostToDevice), "slot upload");
+    }
+    // every active instance's residual window reduced in two launches and read back at once; on
+    // return each active instance's pinned page holds what reduce_launch would have put there
+    int check_all()
+    {
+        const StepArgs* tab = reinterpret_cast<const StepArgs*>(ws + off_tab) + (size_t)cur * count;
+        int rc = hip(launch_residual_batch(stream, tab, reinterpret_cast<const ResidualSlot*>(ws + off_slots),
+                                           count, common.lattice, common.precision,
+                                           node_shift(common) ? 1 : 0, 1, RED_BLOCKS,
+                                           reinterpret_cast<double*>(ws + off_res)), "batched residual");
+        if (rc) return rc;
+        rc = hip(hipMemcpyAsync(pinned, ws + off_res, (size_t)count * 16 * sizeof(double),
+                                hipMemcpyDeviceToHost, stream), "residual readback");
+        if (rc) return rc;
+        rc = hip(hipStreamSynchronize(stream), "residual sync");
+        if (rc) return rc;
+        for (int k = 0; k < count; ++k)
+            if (active[k]) std::memcpy(inst[k]->pinned, pinned + (size_t)k * 16, 10 * sizeof(double));
+        return LBM_MS_OK;
+    }
     hipError_t launch_one()
     {
         const StepArgs* tab = reinterpret_cast<const StepArgs*>(ws + off_tab) + (size_t)cur * count;
@@ -1585,7 +1641,7 @@ size_t instance_bytes(const lbm_ms_params& common, const lbm_ms_instance_desc& d
 
 bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst, int count,
                   std::vector<size_t>* offs, size_t* off_tab, size_t* off_tiles, size_t* off_ent,
-                  size_t* tile_cap, size_t* ent_cap, size_t* total)
+                  size_t* off_slots, size_t* off_res, size_t* tile_cap, size_t* ent_cap, size_t* total)
 {
     // batches step through the tile work list, which has no advective coupling
     if (!common || !inst || count <= 0 || !is_2d(common->lattice) || common->advection) return false;
@@ -1605,6 +1661,10 @@ bool batch_layout(const lbm_ms_params* common, const lbm_ms_instance_desc* inst,
     const size_t ot = take(2ull * count * sizeof(StepArgs));
     const size_t oti = take(tc * 2 * sizeof(int4));
     const size_t oe = take(ec * sizeof(uint32_t));
+    const size_t osl = take((size_t)count * sizeof(ResidualSlot));
+    const size_t ore = take((size_t)count * 16 * sizeof(double));
+    if (off_slots) *off_slots = osl;
+    if (off_res) *off_res = ore;
     if (off_tab) *off_tab = ot;
     if (off_tiles) *off_tiles = oti;
     if (off_ent) *off_ent = oe;
@@ -1622,7 +1682,8 @@ size_t lbm_ms_batch_workspace_bytes(const lbm_ms_params* common, const lbm_ms_in
                                     int count)
 {
     size_t total = 0;
-    if (!batch_layout(common, inst, count, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &total)) {
+    if (!batch_layout(common, inst, count, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, &total)) {
         g_create_err = "invalid batch parameters (D2Q9 common parameters, count > 0, every instance "
                        "valid with a solid mask)";
         return 0;
@@ -1639,6 +1700,7 @@ void lbm_ms_batch_destroy(lbm_ms_batch_t b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->pinned) (void)hipHostFree(b->pinned);
     delete b;
 }
 
@@ -1649,8 +1711,8 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     if (!out) return create_fail(LBM_MS_E_ARG, "out is NULL");
     *out = nullptr;
     std::vector<size_t> offs;
-    size_t ot, oti, oe, tc, ec, total;
-    if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &tc, &ec, &total))
+    size_t ot, oti, oe, osl, ore, tc, ec, total;
+    if (!batch_layout(common, inst, count, &offs, &ot, &oti, &oe, &osl, &ore, &tc, &ec, &total))
         return create_fail(LBM_MS_E_ARG, "invalid batch parameters (2D common parameters without "
                                          "advection, count > 0, every instance valid with a solid "
                                          "mask)");
@@ -1667,6 +1729,8 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
     b->off_tab = ot;
     b->off_tiles = oti;
     b->off_ent = oe;
+    b->off_slots = osl;
+    b->off_res = ore;
     b->tile_cap = tc;
     b->ent_cap = ec;
     b->count = count;
@@ -1682,6 +1746,11 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
         lbm_ms_batch_destroy(b);
         return create_fail(LBM_MS_E_HIP, "stream or event creation failed");
+    }
+    if (hipHostMalloc((void**)&b->pinned, (size_t)count * 16 * sizeof(double)) != hipSuccess) {
+        b->pinned = nullptr;
+        lbm_ms_batch_destroy(b);
+        return create_fail(LBM_MS_E_HIP, "hipHostMalloc of the residual readback failed");
     }
     rc = b->enter();
     for (int k = 0; k < count && rc == LBM_MS_OK; ++k) {
@@ -1704,6 +1773,7 @@ int lbm_ms_batch_create(const lbm_ms_params* common, const lbm_ms_instance_desc*
         rc = b->upload_lists();
     }
     if (rc == LBM_MS_OK) rc = b->upload_tables();
+    if (rc == LBM_MS_OK) rc = b->upload_slots();
     if (rc) {
         const std::string e = b->err.empty() ? std::string(lbm_ms_status_string(rc)) : b->err;
         lbm_ms_batch_destroy(b);
@@ -1778,6 +1848,7 @@ int lbm_ms_batch_init(lbm_ms_batch_t b, const double* X0, int on_device)
         b->active.assign(b->count, 1);
         b->retired_status.assign(b->count, LBM_MS_OK);
         rc = b->upload_active_tiles();
+        if (rc == LBM_MS_OK) rc = b->upload_slots();
     }
     return b->leave(rc);
 }
@@ -1843,6 +1914,7 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
         if (n_active == 0) break;
         if (changed) {
             rc = b->upload_active_tiles();
+            if (rc == LBM_MS_OK) rc = b->upload_slots();
             if (rc) break;
             changed = false;
         }
@@ -1850,10 +1922,13 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
         rc = (b->use_graphs && n == check_every) ? b->step_graph((int)n) : b->step_eager(n);
         if (rc) break;
         taken += n;
+        // every active instance's reduction in one pass over the batch, one wait, then the checks
+        rc = b->check_all();
+        if (rc) break;
         for (int k = 0; k < b->count; ++k) {
             if (!b->active[k]) continue;
             double r = 0;
-            const int rk = lbm_ms_residual(b->inst[k], &r);
+            const int rk = residual_eval(b->inst[k], &r);
             taken_k[k] = taken;
             r_k[k] = r;
             if (rk == LBM_MS_E_HIP) {
@@ -1868,6 +1943,12 @@ int lbm_ms_batch_converge(lbm_ms_batch_t b, double tol, int64_t max_steps, int c
                 changed = true;
             }
         }
+    }
+    // instances that left in the last check leave the work list now, so that later steps and
+    // checks skip them as well
+    if (changed && rc == LBM_MS_OK) {
+        rc = b->upload_active_tiles();
+        if (rc == LBM_MS_OK) rc = b->upload_slots();
     }
     if (steps_taken) std::memcpy(steps_taken, taken_k.data(), sizeof(int64_t) * b->count);
     if (residual) std::memcpy(residual, r_k.data(), sizeof(double) * b->count);

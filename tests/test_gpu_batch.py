@@ -102,6 +102,42 @@ def test_converged_instances_retire():
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_residuals_equal_single_instance_residuals(precision):
+    """The batch reduces every instance's residual window in one pass over the batch; each value
+    is bit for bit the one the instance's own check computes after the same steps."""
+    cases = _cases(js=(0.4, 1.2, 0.8, 1.5))  # no j = 0 instance: none converges by step 300
+    b = lbm_ms.Batch(cases, precision=precision)
+    b.init()
+    steps, r, rc = b.converge(1e-300, 300, check_every=100, raise_on_fail=False)
+    assert rc == lbm_ms.E_NOT_CONVERGED and np.all(steps == 300)
+    for k, c in enumerate(cases):
+        s = lbm_ms.Solver(c, precision=precision)
+        s.init()
+        n, rs, rcs = s.converge(1e-300, 300, check_every=100, raise_on_fail=False)
+        assert n == 300 and rcs == lbm_ms.E_NOT_CONVERGED
+        assert rs == r[k], (k, rs, r[k])
+        s.close()
+    b.close()
+
+
+def test_instance_retired_in_the_last_check_stays_put():
+    """An instance that converges at the last check of a converge call leaves the work list before
+    the call returns: later steps of the batch do not move it."""
+    cases = [inputs.stefan_tube(nx=24, ny=8, tau_ref=20.0, j_A_cm2=0.0, dx=1e-4),
+             inputs.stefan_tube(nx=32, ny=8, tau_ref=20.0, j_A_cm2=1.0, dx=1e-4)]
+    b = lbm_ms.Batch(cases, precision="fp64", tile_y=4)
+    b.init()
+    steps, r, rc = b.converge(1e-10, 100, check_every=100, raise_on_fail=False)
+    assert steps[0] == 100 and r[0] < 1e-10  # the inlet composition: converged at once
+    X0 = b.instance(0).get_fields()
+    X1 = b.instance(1).get_fields()
+    b.step(200)
+    assert np.array_equal(b.instance(0).get_fields(), X0)
+    assert not np.array_equal(b.instance(1).get_fields(), X1)
+    b.close()
+
+
 def test_failed_instance_retires_with_its_status():
     """An instance past its limiting current (a fraction turns negative: the oracle shows it by
     step 100 at 100 A/cm^2 over 2.4 mm) retires with E_NEG_FRACTION; the others still converge."""
