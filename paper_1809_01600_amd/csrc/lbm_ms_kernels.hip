@@ -362,8 +362,9 @@ __global__ __launch_bounds__(32 * TY, (step2d_min_waves<P, NS>())) void k_step2d
     const unsigned pe0 = threadIdx.x < (unsigned)t1.y ? gload<unsigned>(ent, (unsigned)(t1.x + threadIdx.x) * 4u) : dummy;
     const unsigned pe2 = threadIdx.x < (unsigned)t1.w ? gload<unsigned>(ent, (unsigned)(t1.z + threadIdx.x) * 4u) : dummy;
     // Every staging load of a thread is issued before its first store (a loop of load, wait and
-    // store per element costs a memory round trip per element); the NODE shift's references,
-    // which need the indices, follow in a second round.
+    // store per element costs a memory round trip per element): the global shift stages 16-byte
+    // chunks; the NODE shift stages elements, and its references, which need the indices, follow
+    // in a second round (chunks measured slower there).
     if constexpr (NS) {
         stage_plane_refs_pipelined<RX, RY, BS>(a, x0, y0, sI, sC);
     } else {
