@@ -322,7 +322,8 @@ int lbm_ms_batch_step(lbm_ms_batch_t b, int64_t nsteps);
 int lbm_ms_batch_time_steps(lbm_ms_batch_t b, int64_t nsteps, double* ms);
 
 /* Steps in hipGraph-captured chunks of check_every until every instance's residual (as
- * lbm_ms_residual) is below tol or max_steps is reached.  An instance whose check fails
+ * lbm_ms_residual, bit for bit; the checks of all instances run as one reduction over the batch
+ * with one read-back) is below tol or max_steps is reached.  An instance whose check fails
  * (E_NEG_FRACTION when its current exceeds what its pores can supply, E_DIVERGED, E_TAU_CLAMP)
  * retires with that status while the others go on.  Per instance (each pointer may be NULL):
  * steps_taken[k], residual[k], status[k] (0 = converged, E_NOT_CONVERGED, or the failure).
